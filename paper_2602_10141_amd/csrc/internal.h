@@ -1,0 +1,85 @@
+// Internal state of libperm shared by the host translation units.
+#pragma once
+#include <hip/hip_runtime.h>
+
+#include <map>
+#include <string>
+#include <utility>
+#include <vector>
+
+#include "../../include/perm.h"
+#include "kernels.h"
+
+namespace permi {
+
+struct DevBuf {
+    void *p = nullptr;
+    size_t cap = 0;
+};
+
+// One matrix to evaluate (or one Gray index range of it).
+struct MatIn {
+    int variant = 0;
+    int n = 0;
+    uint32_t p = 0;
+    uint64_t src_off = 0;
+    uint32_t out_slot = 0;
+    bool kahan = true;
+    bool full = true;          // whole range [0, 2^(n-1))
+    uint64_t x0 = 0, x1 = 0;   // else this range
+    bool no_scale = false;     // leave the Glynn sum unscaled
+};
+
+// One walk launch.
+struct Group {
+    int variant;
+    int n;
+    bool kahan;
+    bool fused;
+    int nmax_fused;
+    uint32_t first_item;
+    uint32_t count;
+};
+
+struct Plan {
+    std::vector<permk::MatDesc> mats;
+    std::vector<permk::WaveItem> items;
+    std::vector<Group> groups;
+    size_t stage_bytes = 0;
+    size_t nparts = 0;
+};
+
+int fail(int code, const char *fmt, ...) __attribute__((format(printf, 2, 3)));
+
+}  // namespace permi
+
+struct perm_ctx {
+    int device = 0;
+    int num_cus = 1;
+    std::string arch;
+    hipStream_t stream = nullptr;
+    hipEvent_t last_ev = nullptr;
+    hipStream_t last_stream = nullptr;
+    bool has_last = false;
+    size_t budget = 0, used = 0;
+    permi::DevBuf src, stage, partials, outs, plan_buf, ctr;
+    void *pinned = nullptr;
+    size_t pinned_cap = 0;
+    hipEvent_t pinned_ev = nullptr;
+    bool pinned_busy = false;
+    uint64_t ctr_value = 0;
+    int grid_per_cu = 0;
+    std::map<std::pair<int, int>, perm_tune> tune;
+    std::map<int, int> occ;
+};
+
+namespace permi {
+int ensure(perm_ctx *ctx, DevBuf &b, size_t bytes);
+int default_log2_chunk(int variant, int n);
+int log2_chunk_for(const perm_ctx *ctx, int variant, int n);
+int plan(perm_ctx *ctx, const std::vector<MatIn> &in, Plan &pl);
+int begin_call(perm_ctx *ctx, hipStream_t s);
+int end_call(perm_ctx *ctx, hipStream_t s);
+int execute(perm_ctx *ctx, Plan &pl, const void *src, void *out, size_t out_slots, hipStream_t s);
+int validate_plan(const perm_ctx *ctx, const Plan &pl, size_t out_slots);
+}  // namespace permi

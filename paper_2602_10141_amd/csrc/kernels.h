@@ -1,0 +1,105 @@
+// Internal interface between the host library and the HIP kernels of libperm.
+// Not part of the public C ABI (that is include/perm.h).
+#pragma once
+#include <stddef.h>
+#include <stdint.h>
+
+namespace permk {
+
+// Arithmetic variants of the Gray walk.
+enum Variant : int32_t {
+    V_C128 = 0,   // complex128 row sums, Kahan-compensated signed sum
+    V_F64  = 1,   // float64 row sums, Kahan-compensated signed sum
+    V_MODP = 2,   // F_p: exact integer row sums in binary64, FP64 Barrett modmul
+    V_MONT = 3,   // F_p: uint32 residues, 32-bit Montgomery modmul
+    V_COUNT = 4
+};
+
+constexpr int NMAX = 48;        // largest matrix order any kernel handles
+constexpr int WAVE = 64;        // wavefront width on gfx950
+constexpr int BLOCK = 256;      // threads per block of the walk kernels (4 waves)
+
+// MatDesc.flags
+constexpr uint32_t MD_KAHAN    = 1u;   // compensated summation (floats)
+constexpr uint32_t MD_NO_SCALE = 2u;   // finalize leaves the Glynn sum unscaled (range partials)
+
+// One matrix of a launch.  64 bytes, read with scalar loads.
+struct MatDesc {
+    uint64_t src_off;     // byte offset of the caller's matrix in the source buffer
+    uint64_t stage_off;   // byte offset of the staged columns in the stage buffer
+    uint32_t first_part;  // partial-sum slots [first_part, first_part + num_parts)
+    uint32_t num_parts;
+    int32_t  n;
+    int32_t  variant;
+    uint32_t p;           // modulus (F_p variants), else 0
+    uint32_t flags;
+    double   pinv;        // 1/p rounded to binary64 (V_MODP)
+    uint32_t mont_pp;     // -p^{-1} mod 2^32 (V_MONT)
+    uint32_t out_slot;    // result slot (16 bytes each) in the output buffer
+    uint32_t pad[2];
+};
+static_assert(sizeof(MatDesc) == 64, "MatDesc layout");
+
+// One wavefront's share of one matrix.  32 bytes, read with scalar loads.
+// Lane l < nlanes walks the Gray indices [x0 + l*2^log2L, x0 + (l+1)*2^log2L);
+// x0 is a multiple of 2^log2L.  The unscaled signed sum of the wave goes to
+// partial slot `slot`.
+struct WaveItem {
+    uint64_t x0;
+    uint32_t mat;
+    uint32_t slot;
+    uint32_t log2L;
+    uint32_t nlanes;
+    uint32_t pad[2];
+};
+static_assert(sizeof(WaveItem) == 32, "WaveItem layout");
+
+// Bytes of staged columns per matrix for a variant.
+inline size_t stage_bytes(int variant, int n)
+{
+    const size_t nn = (size_t)n * (size_t)n;
+    switch (variant) {
+    case V_C128: return 32 * nn;     // +2A and -2A, complex
+    case V_F64:  return 16 * nn;     // +2A and -2A
+    case V_MODP: return 16 * nn;     // +2A and -2A, balanced residues
+    case V_MONT: return 16 * nn;     // four uint32 arrays
+    }
+    return 0;
+}
+
+// Bytes of one source matrix entry for a variant.
+inline size_t src_entry_bytes(int variant)
+{
+    return variant == V_C128 ? 16 : (variant == V_F64 ? 8 : 4);
+}
+
+// ---------------------------------------------------------------- launchers
+// All return a hipError_t as int and launch on `stream` (a hipStream_t).
+
+// Staging: for each of `nmats` descriptors, read the source matrix at
+// src + src_off and write its staged columns at stage + stage_off.
+int launch_stage(const MatDesc *d_mats, int nmats, const void *src, void *stage, void *stream);
+
+// Walk: `count` wave items, all of one (variant, n) when `fused` is false;
+// with fused = true the matrices may mix variants and orders n <= nmax_fused.
+// `ctr` is a 64-bit device counter whose value at launch time is `base`; the
+// launch adds exactly count + (waves launched) to it, which is returned in
+// *ctr_advance.
+int launch_walk(int variant, int n, bool kahan, bool fused, int nmax_fused,
+                const WaveItem *d_items, uint32_t count, const MatDesc *d_mats,
+                const void *stage, double *partials, unsigned long long *ctr,
+                uint64_t base, int grid_blocks, void *stream, uint64_t *ctr_advance);
+
+// Largest resident blocks per CU for the walk kernel of (variant, n).
+int walk_occupancy(int variant, int n, bool kahan, bool fused, int nmax_fused, int *blocks_per_cu);
+
+// Finalize: per matrix, reduce its partial slots in a fixed order, apply
+// 2^{-(n-1)} (floats) or inv(2)^{n-1} (F_p), and write the 16-byte result slot.
+int launch_finalize(const MatDesc *d_mats, int nmats, const double *partials, void *out,
+                    void *stream);
+
+// Fused-kernel order buckets (a ragged batch with max order n uses the first
+// bucket >= n).
+constexpr int FUSED_BUCKETS[] = {16, 26};
+
+}  // namespace permk

@@ -1,0 +1,812 @@
+// libperm host library: the C ABI of include/perm.h.
+//
+// Every call follows the same pipeline (the hot path of the paper's Sec. 2):
+//   plan     host: split each matrix's Gray index range [0, 2^(n-1)) into
+//                  wavefront items of 64 lanes x 2^c indices, largest first;
+//   stage    device: matrices -> +-2A columns in field-native form;
+//   walk     device: persistent Gray-code Glynn walk, one partial per item;
+//   finalize device: fixed-order reduction per matrix, 2^-(n-1) scaling;
+//   lift     host (CRT only): Garner reconstruction of the signed integer.
+// The host never evaluates any part of a permanent itself.
+#include <hip/hip_runtime.h>
+
+#include <algorithm>
+#include <cmath>
+#include <cstdarg>
+#include <cstdio>
+#include <cstring>
+#include <map>
+#include <mutex>
+#include <new>
+#include <string>
+#include <vector>
+
+#include "../../include/perm.h"
+#include "internal.h"
+#include "kernels.h"
+#include "numth.h"
+
+using namespace permk;
+
+// ------------------------------------------------------------------ errors
+static thread_local std::string g_last_error;
+
+int permi::fail(int code, const char *fmt, ...)
+{
+    char buf[512];
+    va_list ap;
+    va_start(ap, fmt);
+    vsnprintf(buf, sizeof buf, fmt, ap);
+    va_end(ap);
+    g_last_error = buf;
+    return code;
+}
+
+extern "C" const char *perm_strerror(int status)
+{
+    switch (status) {
+    case PERM_OK: return "ok";
+    case PERM_EINVAL: return "invalid argument";
+    case PERM_ERANGE: return "out of range";
+    case PERM_ENOMEM: return "out of memory or over the HBM budget";
+    case PERM_EDEVICE: return "device error";
+    case PERM_EAGAIN: return "queue full, try again";
+    case PERM_ENOTFOUND: return "unknown ticket";
+    case PERM_ECANCELED: return "cancelled";
+    }
+    return "unknown status";
+}
+
+extern "C" const char *perm_last_error(void) { return g_last_error.c_str(); }
+
+#define HIPCHK(expr)                                                                          \
+    do {                                                                                      \
+        hipError_t e_ = (expr);                                                               \
+        if (e_ != hipSuccess)                                                                 \
+            return permi::fail(PERM_EDEVICE, "%s failed: %s", #expr, hipGetErrorString(e_)); \
+    } while (0)
+
+namespace permi {
+
+// ------------------------------------------------------------ device memory
+int ensure(perm_ctx *ctx, DevBuf &b, size_t bytes)
+{
+    if (bytes <= b.cap) return PERM_OK;
+    size_t want = std::max(bytes, b.cap + b.cap / 2);
+    want = (want + 4095) & ~(size_t)4095;
+    if (ctx->used - b.cap + want > ctx->budget) {
+        want = (bytes + 4095) & ~(size_t)4095;
+        if (ctx->used - b.cap + want > ctx->budget)
+            return fail(PERM_ENOMEM, "need %zu bytes of device scratch, budget %zu (in use %zu)",
+                        bytes, ctx->budget, ctx->used);
+    }
+    if (b.p) {
+        // queued work may still read the old buffer
+        if (ctx->has_last) HIPCHK(hipEventSynchronize(ctx->last_ev));
+        HIPCHK(hipFree(b.p));
+        ctx->used -= b.cap;
+        b.p = nullptr;
+        b.cap = 0;
+    }
+    void *p = nullptr;
+    if (hipMalloc(&p, want) != hipSuccess) {
+        (void)hipGetLastError();
+        return fail(PERM_ENOMEM, "hipMalloc(%zu) failed", want);
+    }
+    b.p = p;
+    b.cap = want;
+    ctx->used += want;
+    return PERM_OK;
+}
+
+static int ensure_pinned(perm_ctx *ctx, size_t bytes)
+{
+    if (ctx->pinned_busy) {
+        HIPCHK(hipEventSynchronize(ctx->pinned_ev));
+        ctx->pinned_busy = false;
+    }
+    if (bytes <= ctx->pinned_cap) return PERM_OK;
+    if (ctx->pinned) HIPCHK(hipHostFree(ctx->pinned));
+    ctx->pinned = nullptr;
+    ctx->pinned_cap = 0;
+    const size_t want = std::max(bytes, (size_t)1 << 20);
+    void *p = nullptr;
+    if (hipHostMalloc(&p, want, hipHostMallocDefault) != hipSuccess) {
+        (void)hipGetLastError();
+        return fail(PERM_ENOMEM, "hipHostMalloc(%zu) failed", want);
+    }
+    ctx->pinned = p;
+    ctx->pinned_cap = want;
+    return PERM_OK;
+}
+
+// ------------------------------------------------------------------ tuning
+int default_log2_chunk(int variant, int n)
+{
+    // 64 * 2^c indices per wave item; c in [10, 20] keeps the per-lane seed
+    // (n^2 work) under 1% of the walk and at most 2^20 items per matrix.
+    (void)variant;
+    int c = std::min(std::max(n - 27, 10), 20);
+    return c;
+}
+
+int log2_chunk_for(const perm_ctx *ctx, int variant, int n)
+{
+    const int field = variant == V_MONT ? PERM_MODP : variant;
+    auto it = ctx->tune.find({field, n});
+    if (it != ctx->tune.end() && it->second.log2_chunk > 0) return it->second.log2_chunk;
+    return default_log2_chunk(variant, n);
+}
+
+// ----------------------------------------------------------------- planner
+// Split [x0, x1) into aligned power-of-two blocks and each block into wave
+// items of 64 lanes x 2^c indices (smaller blocks: fewer indices per lane or
+// fewer lanes).
+static void split_range(uint64_t x0, uint64_t x1, int c, uint32_t mat, uint32_t first_slot,
+                        std::vector<WaveItem> &items, uint32_t &nparts)
+{
+    nparts = 0;
+    while (x0 < x1) {
+        int e = x0 ? __builtin_ctzll(x0) : 63;
+        while (e > 0 && (e >= 64 || x0 + (1ull << e) > x1)) --e;
+        const uint64_t B = 1ull << e;
+        const uint64_t wave = 64ull << c;
+        auto push = [&](uint64_t xs, uint32_t log2L, uint32_t lanes) {
+            WaveItem it{};
+            it.x0 = xs;
+            it.mat = mat;
+            it.slot = first_slot + nparts++;
+            it.log2L = log2L;
+            it.nlanes = lanes;
+            items.push_back(it);
+        };
+        if (B >= wave) {
+            for (uint64_t s = 0; s < B; s += wave) push(x0 + s, (uint32_t)c, 64);
+        } else if (B >= 64) {
+            push(x0, (uint32_t)(e - 6), 64);
+        } else {
+            push(x0, 0, (uint32_t)B);
+        }
+        x0 += B;
+    }
+}
+
+int plan(perm_ctx *ctx, const std::vector<MatIn> &in, Plan &pl)
+{
+    pl.mats.clear();
+    pl.items.clear();
+    pl.groups.clear();
+    pl.stage_bytes = 0;
+    pl.nparts = 0;
+    pl.mats.resize(in.size());
+    // Group matrices by launch kernel: one specialized (variant, n) kernel,
+    // the fused kernel of the smallest order bucket, or several specialized
+    // launches when neither fits.
+    bool same = true, fusable = true;
+    int nmax = 0;
+    for (size_t m = 0; m < in.size(); ++m) {
+        const MatIn &a = in[m];
+        if (a.variant != in[0].variant || a.n != in[0].n) same = false;
+        if (a.variant == V_MONT || a.kahan != in[0].kahan) fusable = false;
+        nmax = std::max(nmax, a.n);
+    }
+    if (nmax > FUSED_BUCKETS[1]) fusable = false;
+
+    std::vector<std::vector<uint32_t>> groups;   // matrix ids per launch
+    std::vector<Group> gdesc;
+    if (same || !fusable) {
+        std::map<std::pair<int, int>, size_t> gi;
+        for (size_t m = 0; m < in.size(); ++m) {
+            if (in[m].n == 0) continue;                     // no walk needed
+            auto key = std::make_pair(in[m].variant, in[m].n);
+            auto it = gi.find(key);
+            if (it == gi.end()) {
+                gi[key] = groups.size();
+                groups.push_back({(uint32_t)m});
+                Group g{};
+                g.variant = in[m].variant;
+                g.n = in[m].n;
+                g.kahan = in[m].kahan;
+                g.fused = false;
+                gdesc.push_back(g);
+            } else {
+                groups[it->second].push_back((uint32_t)m);
+            }
+        }
+    } else {
+        Group g{};
+        g.fused = true;
+        g.nmax_fused = nmax <= FUSED_BUCKETS[0] ? FUSED_BUCKETS[0] : FUSED_BUCKETS[1];
+        g.kahan = in[0].kahan;
+        g.variant = -1;
+        g.n = nmax;
+        std::vector<uint32_t> ids;
+        for (size_t m = 0; m < in.size(); ++m)
+            if (in[m].n > 0) ids.push_back((uint32_t)m);
+        if (!ids.empty()) {
+            groups.push_back(ids);
+            gdesc.push_back(g);
+        }
+    }
+
+    // descriptors (all matrices, including n = 0 ones, in input order)
+    for (size_t m = 0; m < in.size(); ++m) {
+        const MatIn &a = in[m];
+        MatDesc &d = pl.mats[m];
+        std::memset(&d, 0, sizeof d);
+        d.src_off = a.src_off;
+        d.stage_off = pl.stage_bytes;
+        d.n = a.n;
+        d.variant = a.variant;
+        d.p = a.p;
+        d.flags = (a.kahan ? MD_KAHAN : 0) | (a.no_scale ? MD_NO_SCALE : 0);
+        d.pinv = a.p ? 1.0 / (double)a.p : 0.0;
+        d.mont_pp = (a.variant == V_MONT) ? permh::mont_pprime(a.p) : 0;
+        d.out_slot = a.out_slot;
+        if (a.n > 0) pl.stage_bytes += (stage_bytes(a.variant, a.n) + 255) & ~(size_t)255;
+    }
+    // items per group, each group sorted largest first (stable)
+    for (size_t g = 0; g < groups.size(); ++g) {
+        Group gd = gdesc[g];
+        gd.first_item = (uint32_t)pl.items.size();
+        std::vector<WaveItem> gi;
+        for (uint32_t m : groups[g]) {
+            const MatIn &a = in[m];
+            MatDesc &d = pl.mats[m];
+            const int c = log2_chunk_for(ctx, a.variant, a.n);
+            const uint64_t T = 1ull << (a.n - 1);
+            const uint64_t x0 = a.full ? 0 : a.x0;
+            const uint64_t x1 = a.full ? T : a.x1;
+            uint32_t np = 0;
+            d.first_part = (uint32_t)pl.nparts;
+            split_range(x0, x1, c, m, (uint32_t)pl.nparts, gi, np);
+            d.num_parts = np;
+            pl.nparts += np;
+        }
+        std::stable_sort(gi.begin(), gi.end(), [&](const WaveItem &u, const WaveItem &v) {
+            const double cu = (double)u.nlanes * std::ldexp(1.0, (int)u.log2L) * in[u.mat].n;
+            const double cv = (double)v.nlanes * std::ldexp(1.0, (int)v.log2L) * in[v.mat].n;
+            return cu > cv;
+        });
+        pl.items.insert(pl.items.end(), gi.begin(), gi.end());
+        gd.count = (uint32_t)gi.size();
+        pl.groups.push_back(gd);
+    }
+    return PERM_OK;
+}
+
+// Blocks per CU for a group's kernel (cached).
+static int occupancy(perm_ctx *ctx, const Group &g)
+{
+    const int key = g.fused ? (1000 + g.nmax_fused * 2 + (g.kahan ? 1 : 0))
+                            : (g.variant * 200 + g.n * 2 + (g.kahan ? 1 : 0));
+    auto it = ctx->occ.find(key);
+    if (it != ctx->occ.end()) return it->second;
+    int nb = 1;
+    if (walk_occupancy(g.variant, g.n, g.kahan, g.fused, g.nmax_fused, &nb) != 0 || nb < 1) nb = 1;
+    ctx->occ[key] = nb;
+    return nb;
+}
+
+// Order this call after the context's previous call when the stream changes.
+int begin_call(perm_ctx *ctx, hipStream_t s)
+{
+    HIPCHK(hipSetDevice(ctx->device));
+    if (ctx->has_last && s != ctx->last_stream) HIPCHK(hipStreamWaitEvent(s, ctx->last_ev, 0));
+    return PERM_OK;
+}
+
+int end_call(perm_ctx *ctx, hipStream_t s)
+{
+    HIPCHK(hipEventRecord(ctx->last_ev, s));
+    ctx->last_stream = s;
+    ctx->has_last = true;
+    return PERM_OK;
+}
+
+// Check on the host that every descriptor a kernel will dereference stays
+// inside its buffer, so that a planning mistake is an error, not a GPU fault.
+int validate_plan(const perm_ctx *ctx, const Plan &pl, size_t out_slots)
+{
+    const size_t nm = pl.mats.size();
+    for (size_t m = 0; m < nm; ++m) {
+        const MatDesc &d = pl.mats[m];
+        if (d.n < 0 || d.n > NMAX || d.variant < 0 || d.variant >= V_COUNT)
+            return fail(PERM_EINVAL, "plan: bad matrix %zu", m);
+        if (d.n > 0 && d.stage_off + stage_bytes(d.variant, d.n) > ctx->stage.cap)
+            return fail(PERM_EINVAL, "plan: staged matrix %zu outside the stage buffer", m);
+        if ((size_t)d.first_part + d.num_parts > pl.nparts || pl.nparts * 16 > ctx->partials.cap)
+            return fail(PERM_EINVAL, "plan: partial slots of matrix %zu out of range", m);
+        if (d.out_slot >= out_slots) return fail(PERM_EINVAL, "plan: output slot of matrix %zu", m);
+        if ((d.variant == V_MODP || d.variant == V_MONT) && !(d.p & 1u))
+            return fail(PERM_EINVAL, "plan: even modulus");
+    }
+    for (const Group &g : pl.groups)
+        if ((size_t)g.first_item + g.count > pl.items.size())
+            return fail(PERM_EINVAL, "plan: launch group out of range");
+    for (size_t i = 0; i < pl.items.size(); ++i) {
+        const WaveItem &it = pl.items[i];
+        if (it.mat >= nm) return fail(PERM_EINVAL, "plan: item %zu names matrix %u", i, it.mat);
+        const MatDesc &d = pl.mats[it.mat];
+        if (d.n < 1 || it.slot < d.first_part || it.slot >= d.first_part + d.num_parts)
+            return fail(PERM_EINVAL, "plan: item %zu slot out of its matrix's range", i);
+        if (it.nlanes < 1 || it.nlanes > 64 || it.log2L > 24 || (it.x0 & ((1ull << it.log2L) - 1)))
+            return fail(PERM_EINVAL, "plan: item %zu has a bad shape", i);
+        const uint64_t end = it.x0 + ((uint64_t)it.nlanes << it.log2L);
+        if (end > (1ull << (d.n - 1)))
+            return fail(PERM_EINVAL, "plan: item %zu runs past 2^(n-1)", i);
+        if ((d.variant == V_MODP) && it.log2L > 20)
+            return fail(PERM_EINVAL, "plan: F_p chunk longer than 2^20");
+    }
+    return PERM_OK;
+}
+
+// Upload the plan, stage, walk, finalize.  `src` holds the matrices (device),
+// `out` receives 16-byte result slots (device).
+int execute(perm_ctx *ctx, Plan &pl, const void *src, void *out, size_t out_slots, hipStream_t s)
+{
+    const size_t mb = pl.mats.size() * sizeof(MatDesc);
+    const size_t ib = pl.items.size() * sizeof(WaveItem);
+    int rc;
+    if ((rc = ensure(ctx, ctx->plan_buf, mb + ib + 64)) != PERM_OK) return rc;
+    if ((rc = ensure(ctx, ctx->stage, std::max<size_t>(pl.stage_bytes, 256))) != PERM_OK) return rc;
+    if ((rc = ensure(ctx, ctx->partials, std::max<size_t>(pl.nparts, 1) * 16)) != PERM_OK) return rc;
+    if ((rc = validate_plan(ctx, pl, out_slots)) != PERM_OK) return rc;
+    if ((rc = ensure_pinned(ctx, mb + ib)) != PERM_OK) return rc;
+    std::memcpy(ctx->pinned, pl.mats.data(), mb);
+    if (ib) std::memcpy((char *)ctx->pinned + mb, pl.items.data(), ib);
+    HIPCHK(hipMemcpyAsync(ctx->plan_buf.p, ctx->pinned, mb + ib, hipMemcpyHostToDevice, s));
+    HIPCHK(hipEventRecord(ctx->pinned_ev, s));
+    ctx->pinned_busy = true;
+    const MatDesc *d_mats = (const MatDesc *)ctx->plan_buf.p;
+    const WaveItem *d_items = (const WaveItem *)((char *)ctx->plan_buf.p + mb);
+
+    HIPCHK((hipError_t)launch_stage(d_mats, (int)pl.mats.size(), src, ctx->stage.p, s));
+    for (const Group &g : pl.groups) {
+        if (!g.count) continue;
+        const int occ = occupancy(ctx, g);
+        const int per_cu = ctx->grid_per_cu > 0 ? std::min(ctx->grid_per_cu, occ) : occ;
+        const int blocks_needed = (int)((g.count + (BLOCK / WAVE) - 1) / (BLOCK / WAVE));
+        const int grid = std::max(1, std::min(blocks_needed, per_cu * ctx->num_cus));
+        uint64_t adv = 0;
+        HIPCHK((hipError_t)launch_walk(g.variant, g.n, g.kahan, g.fused, g.nmax_fused,
+                                       d_items + g.first_item, g.count, d_mats, ctx->stage.p,
+                                       (double *)ctx->partials.p,
+                                       (unsigned long long *)ctx->ctr.p, ctx->ctr_value, grid, s,
+                                       &adv));
+        ctx->ctr_value += adv;
+    }
+    HIPCHK((hipError_t)launch_finalize(d_mats, (int)pl.mats.size(), (const double *)ctx->partials.p,
+                                       out, s));
+    return PERM_OK;
+}
+
+}  // namespace permi
+
+using namespace permi;
+
+// ----------------------------------------------------------------- context
+extern "C" int perm_ctx_create(int device, size_t hbm_budget, perm_ctx **out)
+{
+    if (!out) return fail(PERM_EINVAL, "out is NULL");
+    *out = nullptr;
+    int ndev = 0;
+    if (hipGetDeviceCount(&ndev) != hipSuccess || ndev <= 0) {
+        (void)hipGetLastError();
+        return fail(PERM_EDEVICE, "no HIP device available");
+    }
+    if (device < 0 || device >= ndev) return fail(PERM_EDEVICE, "device %d out of range", device);
+    HIPCHK(hipSetDevice(device));
+    hipDeviceProp_t prop;
+    HIPCHK(hipGetDeviceProperties(&prop, device));
+    perm_ctx *c = new (std::nothrow) perm_ctx();
+    if (!c) return fail(PERM_ENOMEM, "host allocation failed");
+    c->device = device;
+    c->num_cus = prop.multiProcessorCount;
+    c->arch = prop.gcnArchName;
+    c->budget = hbm_budget ? hbm_budget : prop.totalGlobalMem / 4;
+    if (hipStreamCreateWithFlags(&c->stream, hipStreamNonBlocking) != hipSuccess ||
+        hipEventCreateWithFlags(&c->last_ev, hipEventDisableTiming) != hipSuccess ||
+        hipEventCreateWithFlags(&c->pinned_ev, hipEventDisableTiming) != hipSuccess) {
+        delete c;
+        return fail(PERM_EDEVICE, "stream/event creation failed");
+    }
+    int rc = ensure(c, c->ctr, 256);
+    if (rc != PERM_OK) { perm_ctx_destroy(c); return rc; }
+    if (hipMemset(c->ctr.p, 0, 256) != hipSuccess) {
+        perm_ctx_destroy(c);
+        return fail(PERM_EDEVICE, "counter init failed");
+    }
+    c->ctr_value = 0;
+    *out = c;
+    return PERM_OK;
+}
+
+extern "C" void perm_ctx_destroy(perm_ctx *c)
+{
+    if (!c) return;
+    (void)hipSetDevice(c->device);
+    if (c->stream) (void)hipStreamSynchronize(c->stream);
+    if (c->has_last) (void)hipEventSynchronize(c->last_ev);
+    for (DevBuf *b : {&c->src, &c->stage, &c->partials, &c->outs, &c->plan_buf, &c->ctr})
+        if (b->p) (void)hipFree(b->p);
+    if (c->pinned) (void)hipHostFree(c->pinned);
+    if (c->last_ev) (void)hipEventDestroy(c->last_ev);
+    if (c->pinned_ev) (void)hipEventDestroy(c->pinned_ev);
+    if (c->stream) (void)hipStreamDestroy(c->stream);
+    delete c;
+}
+
+// ---------------------------------------------------------- argument checks
+static bool modulus_ok(uint32_t p) { return p >= 3 && (p & 1u) && p < (1u << 31); }
+
+static int variant_of(int field, unsigned flags)
+{
+    switch (field) {
+    case PERM_C128: return V_C128;
+    case PERM_F64: return V_F64;
+    case PERM_MODP: return (flags & PERM_MONTGOMERY) ? V_MONT : V_MODP;
+    }
+    return -1;
+}
+
+// Bring the matrices to the device: returns the device pointer to use as the
+// staging source.
+static int source_on_device(perm_ctx *ctx, const void *data, size_t bytes, unsigned flags,
+                            hipStream_t s, const void **dev)
+{
+    if (flags & PERM_DEVICE_PTRS) {
+        *dev = data;
+        return PERM_OK;
+    }
+    int rc = ensure(ctx, ctx->src, std::max<size_t>(bytes, 256));
+    if (rc != PERM_OK) return rc;
+    if (bytes) HIPCHK(hipMemcpyAsync(ctx->src.p, data, bytes, hipMemcpyHostToDevice, s));
+    *dev = ctx->src.p;
+    return PERM_OK;
+}
+
+// One matrix, one result slot of `out_bytes` copied to `out`.
+static int single(perm_ctx *ctx, int variant, const void *A, int n, uint32_t p, void *out,
+                  size_t out_bytes, unsigned flags, void *stream)
+{
+    if (!ctx) return fail(PERM_EINVAL, "ctx is NULL");
+    if (n < 0 || n > PERM_NMAX) return fail(PERM_EINVAL, "n = %d outside [0, %d]", n, PERM_NMAX);
+    if (!out || (n > 0 && !A)) return fail(PERM_EINVAL, "NULL matrix or output pointer");
+    hipStream_t s = stream ? (hipStream_t)stream : ctx->stream;
+    int rc = begin_call(ctx, s);
+    if (rc != PERM_OK) return rc;
+    const void *src = nullptr;
+    const size_t bytes = (size_t)n * n * src_entry_bytes(variant);
+    if ((rc = source_on_device(ctx, A, bytes, flags, s, &src)) != PERM_OK) return rc;
+    std::vector<MatIn> in(1);
+    in[0].variant = variant;
+    in[0].n = n;
+    in[0].p = p;
+    in[0].kahan = !(flags & PERM_NO_KAHAN);
+    in[0].full = true;
+    Plan pl;
+    if ((rc = plan(ctx, in, pl)) != PERM_OK) return rc;
+    if ((rc = ensure(ctx, ctx->outs, 256)) != PERM_OK) return rc;
+    if ((rc = execute(ctx, pl, src, ctx->outs.p, 1, s)) != PERM_OK) return rc;
+    if (flags & PERM_DEVICE_PTRS) {
+        HIPCHK(hipMemcpyAsync(out, ctx->outs.p, out_bytes, hipMemcpyDeviceToDevice, s));
+        return end_call(ctx, s);
+    }
+    HIPCHK(hipMemcpyAsync(out, ctx->outs.p, out_bytes, hipMemcpyDeviceToHost, s));
+    if ((rc = end_call(ctx, s)) != PERM_OK) return rc;
+    HIPCHK(hipStreamSynchronize(s));
+    return PERM_OK;
+}
+
+extern "C" int perm_c128(perm_ctx *ctx, const double *A, int n, double *out, unsigned flags,
+                         void *stream)
+{
+    return single(ctx, V_C128, A, n, 0, out, 16, flags, stream);
+}
+
+extern "C" int perm_f64(perm_ctx *ctx, const double *A, int n, double *out, unsigned flags,
+                        void *stream)
+{
+    return single(ctx, V_F64, A, n, 0, out, 8, flags, stream);
+}
+
+extern "C" int perm_modp(perm_ctx *ctx, const uint32_t *A, int n, uint32_t p, uint32_t *out,
+                         unsigned flags, void *stream)
+{
+    if (!modulus_ok(p)) return fail(PERM_EINVAL, "modulus %u must be odd with 3 <= p < 2^31", p);
+    return single(ctx, variant_of(PERM_MODP, flags), A, n, p, out, 4, flags, stream);
+}
+
+// ------------------------------------------------------------------- batch
+static int check_item(const perm_item &it, uint64_t data_addr)
+{
+    if (it.n < 0 || it.n > PERM_NMAX) return fail(PERM_EINVAL, "n = %d outside [0, %d]", it.n, PERM_NMAX);
+    if (it.field != PERM_C128 && it.field != PERM_F64 && it.field != PERM_MODP)
+        return fail(PERM_EINVAL, "unknown field %d", it.field);
+    if (it.field == PERM_MODP && !modulus_ok(it.p))
+        return fail(PERM_EINVAL, "modulus %u must be odd with 3 <= p < 2^31", it.p);
+    if (it.reserved != 0) return fail(PERM_EINVAL, "reserved field must be 0");
+    const uint64_t align = it.field == PERM_MODP ? 4 : 8;
+    if ((data_addr + it.offset) % align)
+        return fail(PERM_EINVAL, "matrix at offset %llu is not %llu-byte aligned",
+                    (unsigned long long)it.offset, (unsigned long long)align);
+    return PERM_OK;
+}
+
+extern "C" int perm_batch(perm_ctx *ctx, const perm_item *items, int count, const void *data,
+                          void *out, int *bad_index, unsigned flags, void *stream)
+{
+    if (bad_index) *bad_index = -1;
+    if (!ctx) return fail(PERM_EINVAL, "ctx is NULL");
+    if (count < 0 || (count > 0 && (!items || !out))) return fail(PERM_EINVAL, "bad count or NULL pointer");
+    if (count == 0) return PERM_OK;
+    uint64_t span = 0;
+    bool any_data = false;
+    for (int i = 0; i < count; ++i) {
+        int rc = check_item(items[i], (uint64_t)(uintptr_t)data);
+        if (rc != PERM_OK) {
+            if (bad_index) *bad_index = i;
+            return rc;
+        }
+        const uint64_t bytes = (uint64_t)items[i].n * items[i].n *
+                               src_entry_bytes(variant_of(items[i].field, flags));
+        if (bytes) any_data = true;
+        span = std::max(span, items[i].offset + bytes);
+    }
+    if (any_data && !data) return fail(PERM_EINVAL, "data is NULL");
+    hipStream_t s = stream ? (hipStream_t)stream : ctx->stream;
+    int rc = begin_call(ctx, s);
+    if (rc != PERM_OK) return rc;
+    const void *src = nullptr;
+    if ((rc = source_on_device(ctx, data, span, flags, s, &src)) != PERM_OK) return rc;
+    std::vector<MatIn> in(count);
+    for (int i = 0; i < count; ++i) {
+        in[i].variant = variant_of(items[i].field, flags);
+        in[i].n = items[i].n;
+        in[i].p = items[i].field == PERM_MODP ? items[i].p : 0;
+        in[i].src_off = items[i].offset;
+        in[i].out_slot = (uint32_t)i;
+        in[i].kahan = !(flags & PERM_NO_KAHAN);
+        in[i].full = true;
+    }
+    Plan pl;
+    if ((rc = plan(ctx, in, pl)) != PERM_OK) return rc;
+    void *dout = out;
+    if (!(flags & PERM_DEVICE_PTRS)) {
+        if ((rc = ensure(ctx, ctx->outs, (size_t)count * 16)) != PERM_OK) return rc;
+        dout = ctx->outs.p;
+    }
+    if ((rc = execute(ctx, pl, src, dout, (size_t)count, s)) != PERM_OK) return rc;
+    if (flags & PERM_DEVICE_PTRS) return end_call(ctx, s);
+    HIPCHK(hipMemcpyAsync(out, dout, (size_t)count * 16, hipMemcpyDeviceToHost, s));
+    if ((rc = end_call(ctx, s)) != PERM_OK) return rc;
+    HIPCHK(hipStreamSynchronize(s));
+    return PERM_OK;
+}
+
+// ------------------------------------------------------------------- range
+extern "C" int perm_range(perm_ctx *ctx, const perm_item *item, const void *data, uint64_t x0,
+                          uint64_t x1, void *out16, unsigned flags, void *stream)
+{
+    if (!ctx || !item || !out16) return fail(PERM_EINVAL, "NULL argument");
+    int rc = check_item(*item, (uint64_t)(uintptr_t)data);
+    if (rc != PERM_OK) return rc;
+    if (item->n < 1) return fail(PERM_EINVAL, "range needs n >= 1");
+    const uint64_t T = 1ull << (item->n - 1);
+    if (x0 > x1 || x1 > T) return fail(PERM_EINVAL, "range [%llu, %llu) outside [0, 2^%d)",
+                                       (unsigned long long)x0, (unsigned long long)x1, item->n - 1);
+    if (!data) return fail(PERM_EINVAL, "data is NULL");
+    hipStream_t s = stream ? (hipStream_t)stream : ctx->stream;
+    if ((rc = begin_call(ctx, s)) != PERM_OK) return rc;
+    const int variant = variant_of(item->field, flags);
+    const uint64_t bytes = (uint64_t)item->n * item->n * src_entry_bytes(variant);
+    const void *src = nullptr;
+    if (flags & PERM_DEVICE_PTRS) src = (const char *)data + item->offset;
+    else if ((rc = source_on_device(ctx, (const char *)data + item->offset, bytes, flags, s, &src)) != PERM_OK)
+        return rc;
+    std::vector<MatIn> in(1);
+    in[0].variant = variant;
+    in[0].n = item->n;
+    in[0].p = item->field == PERM_MODP ? item->p : 0;
+    in[0].kahan = !(flags & PERM_NO_KAHAN);
+    in[0].full = false;
+    in[0].x0 = x0;
+    in[0].x1 = x1;
+    in[0].no_scale = true;
+    Plan pl;
+    if ((rc = plan(ctx, in, pl)) != PERM_OK) return rc;
+    if ((rc = ensure(ctx, ctx->outs, 256)) != PERM_OK) return rc;
+    if (x0 == x1) {
+        // empty range: the sum is zero; finalize writes zero for num_parts = 0
+        // only when n = 0, so fill the slot on the device
+        HIPCHK(hipMemsetAsync(ctx->outs.p, 0, 16, s));
+    } else if ((rc = execute(ctx, pl, src, ctx->outs.p, 1, s)) != PERM_OK) {
+        return rc;
+    }
+    HIPCHK(hipMemcpyAsync(out16, ctx->outs.p, 16, hipMemcpyDeviceToHost, s));
+    if ((rc = end_call(ctx, s)) != PERM_OK) return rc;
+    HIPCHK(hipStreamSynchronize(s));
+    return PERM_OK;
+}
+
+// --------------------------------------------------------------------- CRT
+static int write_limbs(const permh::BigU &mag, int sgn, uint64_t *limbs, int max_limbs,
+                       int *nlimbs, int *sign)
+{
+    if ((int)mag.limb.size() > max_limbs)
+        return fail(PERM_ERANGE, "result needs %zu limbs, max_limbs = %d", mag.limb.size(), max_limbs);
+    for (size_t i = 0; i < mag.limb.size(); ++i) limbs[i] = mag.limb[i];
+    *nlimbs = (int)mag.limb.size();
+    *sign = sgn;
+    return PERM_OK;
+}
+
+static int check_primes(const uint32_t *primes, int k, double log2_bound)
+{
+    if (!primes || k < 1) return fail(PERM_EINVAL, "need k >= 1 primes");
+    for (int i = 0; i < k; ++i) {
+        if (!modulus_ok(primes[i]) || !permh::is_prime_u32(primes[i]))
+            return fail(PERM_EINVAL, "modulus %u is not an odd prime below 2^31", primes[i]);
+        for (int j = 0; j < i; ++j)
+            if (primes[j] == primes[i]) return fail(PERM_EINVAL, "duplicate prime %u", primes[i]);
+    }
+    if (!(log2_bound >= 0.0) || !std::isfinite(log2_bound))
+        return fail(PERM_EINVAL, "log2_bound must be finite and >= 0");
+    // M > 2^(bound + 1), with a safety margin for the float sum of logs
+    if (permh::log2_product(primes, k) <= log2_bound + 1.0 + 1e-9)
+        return fail(PERM_ERANGE, "product of the primes (2^%.3f) does not exceed 2^(%.3f + 1)",
+                    permh::log2_product(primes, k), log2_bound);
+    return PERM_OK;
+}
+
+extern "C" int perm_crt_lift(const uint32_t *residues, const uint32_t *primes, int k,
+                             double log2_bound, uint64_t *limbs, int max_limbs, int *nlimbs,
+                             int *sign)
+{
+    if (!residues || !limbs || !nlimbs || !sign) return fail(PERM_EINVAL, "NULL argument");
+    int rc = check_primes(primes, k, log2_bound);
+    if (rc != PERM_OK) return rc;
+    permh::BigU mag;
+    int sg = 0;
+    if (!permh::garner_lift(residues, primes, k, mag, sg)) return fail(PERM_EINVAL, "lift failed");
+    return write_limbs(mag, sg, limbs, max_limbs, nlimbs, sign);
+}
+
+extern "C" int perm_crt_int(perm_ctx *ctx, const uint32_t *mats, const uint32_t *primes, int k,
+                            int n, double log2_bound, uint64_t *limbs, int max_limbs, int *nlimbs,
+                            int *sign, uint32_t *residues_out, unsigned flags, void *stream)
+{
+    if (!ctx || !limbs || !nlimbs || !sign) return fail(PERM_EINVAL, "NULL argument");
+    if (n < 0 || n > PERM_NMAX) return fail(PERM_EINVAL, "n = %d outside [0, %d]", n, PERM_NMAX);
+    if (n > 0 && !mats) return fail(PERM_EINVAL, "mats is NULL");
+    int rc = check_primes(primes, k, log2_bound);
+    if (rc != PERM_OK) return rc;
+    hipStream_t s = stream ? (hipStream_t)stream : ctx->stream;
+    if ((rc = begin_call(ctx, s)) != PERM_OK) return rc;
+    const int variant = variant_of(PERM_MODP, flags);
+    const size_t per = (size_t)n * n * 4;
+    const void *src = nullptr;
+    if ((rc = source_on_device(ctx, mats, per * k, flags, s, &src)) != PERM_OK) return rc;
+    std::vector<MatIn> in(k);
+    for (int i = 0; i < k; ++i) {
+        in[i].variant = variant;
+        in[i].n = n;
+        in[i].p = primes[i];
+        in[i].src_off = per * i;
+        in[i].out_slot = (uint32_t)i;
+        in[i].full = true;
+    }
+    Plan pl;
+    if ((rc = plan(ctx, in, pl)) != PERM_OK) return rc;
+    if ((rc = ensure(ctx, ctx->outs, (size_t)k * 16)) != PERM_OK) return rc;
+    if ((rc = execute(ctx, pl, src, ctx->outs.p, (size_t)k, s)) != PERM_OK) return rc;
+    std::vector<uint32_t> slots((size_t)k * 4);
+    HIPCHK(hipMemcpyAsync(slots.data(), ctx->outs.p, (size_t)k * 16, hipMemcpyDeviceToHost, s));
+    if ((rc = end_call(ctx, s)) != PERM_OK) return rc;
+    HIPCHK(hipStreamSynchronize(s));
+    std::vector<uint32_t> res(k);
+    for (int i = 0; i < k; ++i) res[i] = slots[4 * (size_t)i];
+    permh::BigU mag;
+    int sg = 0;
+    if (!permh::garner_lift(res.data(), primes, k, mag, sg)) return fail(PERM_EINVAL, "lift failed");
+    if ((rc = write_limbs(mag, sg, limbs, max_limbs, nlimbs, sign)) != PERM_OK) return rc;
+    if (residues_out) std::memcpy(residues_out, res.data(), (size_t)k * 4);
+    return PERM_OK;
+}
+
+// ------------------------------------------------------------------ helpers
+extern "C" int perm_schur_primes(int n, int extra, uint32_t *primes, int max_primes, int *k)
+{
+    if (n < 1 || extra < 0 || !primes || !k) return fail(PERM_EINVAL, "bad argument");
+    for (int cnt = 1; cnt <= 64; ++cnt) {
+        std::vector<uint32_t> ps = permh::primes_1_mod_n(n, cnt);
+        if ((int)ps.size() < cnt) return fail(PERM_ERANGE, "not enough 31-bit primes = 1 mod %d", n);
+        if (permh::schur_bound_ok(n, ps)) {
+            ps = permh::primes_1_mod_n(n, cnt + extra);
+            if ((int)ps.size() < cnt + extra) return fail(PERM_ERANGE, "not enough primes");
+            if ((int)ps.size() > max_primes) return fail(PERM_ERANGE, "max_primes too small");
+            std::copy(ps.begin(), ps.end(), primes);
+            *k = (int)ps.size();
+            return PERM_OK;
+        }
+    }
+    return fail(PERM_ERANGE, "bound not reached with 64 primes");
+}
+
+extern "C" int perm_schur_residues(int n, uint32_t p, uint32_t *out)
+{
+    if (n < 1 || !out) return fail(PERM_EINVAL, "bad argument");
+    if (!permh::is_prime_u32(p) || (p - 1) % (uint32_t)n)
+        return fail(PERM_EINVAL, "p = %u is not a prime = 1 (mod %d)", p, n);
+    const uint32_t g = permh::root_of_unity(n, p);
+    if (!g) return fail(PERM_EINVAL, "no primitive root of unity");
+    for (int j = 0; j < n; ++j)
+        for (int k = 0; k < n; ++k)
+            out[(size_t)j * n + k] = (uint32_t)permh::powmod(g, (uint64_t)j * k, p);
+    return PERM_OK;
+}
+
+// ------------------------------------------------------------------ tuning
+static bool tune_key_ok(int field, int n)
+{
+    return (field == PERM_C128 || field == PERM_F64 || field == PERM_MODP) && n >= 1 && n <= PERM_NMAX;
+}
+
+extern "C" int perm_tune_get(perm_ctx *ctx, int field, int n, perm_tune *out)
+{
+    if (!ctx || !out || !tune_key_ok(field, n)) return fail(PERM_EINVAL, "bad argument");
+    auto it = ctx->tune.find({field, n});
+    perm_tune t{};
+    if (it != ctx->tune.end()) t = it->second;
+    if (t.log2_chunk <= 0) t.log2_chunk = default_log2_chunk(field, n);
+    *out = t;
+    return PERM_OK;
+}
+
+extern "C" int perm_tune_set(perm_ctx *ctx, int field, int n, const perm_tune *t)
+{
+    if (!ctx || !t || !tune_key_ok(field, n)) return fail(PERM_EINVAL, "bad argument");
+    if (t->log2_chunk < 0 || t->log2_chunk > 24 || t->grid_per_cu < 0)
+        return fail(PERM_EINVAL, "log2_chunk must be in [0, 24], grid_per_cu >= 0");
+    if (field == PERM_MODP && t->log2_chunk > 20)
+        return fail(PERM_EINVAL, "F_p chunks are limited to 2^20 indices per lane");
+    ctx->tune[{field, n}] = *t;
+    return PERM_OK;
+}
+
+extern "C" int perm_tune_save(perm_ctx *ctx, const char *path)
+{
+    if (!ctx || !path) return fail(PERM_EINVAL, "bad argument");
+    FILE *f = fopen(path, "w");
+    if (!f) return fail(PERM_EINVAL, "cannot open %s", path);
+    fprintf(f, "# libperm tuning table: field n log2_chunk grid_per_cu\n# arch %s\n",
+            ctx->arch.c_str());
+    for (auto &kv : ctx->tune)
+        fprintf(f, "%d %d %d %d\n", kv.first.first, kv.first.second, kv.second.log2_chunk,
+                kv.second.grid_per_cu);
+    fclose(f);
+    return PERM_OK;
+}
+
+extern "C" int perm_tune_load(perm_ctx *ctx, const char *path)
+{
+    if (!ctx || !path) return fail(PERM_EINVAL, "bad argument");
+    FILE *f = fopen(path, "r");
+    if (!f) return fail(PERM_EINVAL, "cannot open %s", path);
+    char line[256];
+    std::map<std::pair<int, int>, perm_tune> tab;
+    while (fgets(line, sizeof line, f)) {
+        if (line[0] == '#' || line[0] == '\n') continue;
+        int field, n, c, g;
+        if (sscanf(line, "%d %d %d %d", &field, &n, &c, &g) != 4 || !tune_key_ok(field, n) || c < 0 ||
+            c > 24 || g < 0) {
+            fclose(f);
+            return fail(PERM_EINVAL, "malformed line in %s: %s", path, line);
+        }
+        tab[{field, n}] = perm_tune{c, g};
+    }
+    fclose(f);
+    ctx->tune = tab;
+    return PERM_OK;
+}

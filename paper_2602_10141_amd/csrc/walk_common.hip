@@ -1,0 +1,215 @@
+// Staging, finalize and launch code for the Gray walk kernels.
+// The walk itself is described in walk_impl.h; its instantiations for every
+// (variant, n) live in the walk_inst_*.hip translation units.
+#include "walk_impl.h"
+
+namespace permk {
+
+// ----------------------------------------------------------------- staging
+// Staged layout, column-major (column k, row i at k*n + i):
+//   c128, f64, F_p (Barrett): [+2A][-2A] as binary64 (complex: re, im pairs);
+//                             F_p entries are first mapped to balanced
+//                             residues in [-(p-1)/2, (p-1)/2];
+//   F_p (Montgomery):         [2a mod p][(p - 2a) mod p][a][(p - a) mod p] as uint32.
+// Entries of F_p matrices are reduced mod p first.
+__global__ __launch_bounds__(256) void stage_kernel(const MatDesc *mats, const char *src, char *stage)
+{
+    const MatDesc md = mats[blockIdx.x];
+    const int n = md.n;
+    const int nn = n * n;
+    const char *s = src + md.src_off;
+    char *d = stage + md.stage_off;
+    for (int e = threadIdx.x; e < nn; e += blockDim.x) {
+        const int i = e / n;          // source row
+        const int k = e - i * n;      // source column
+        const int t = k * n + i;      // staged: column k, row i
+        switch (md.variant) {
+        case V_C128: {
+            const double *a = (const double *)s + 2 * (size_t)e;
+            double *o = (double *)d;
+            o[2 * t] = 2.0 * a[0];
+            o[2 * t + 1] = 2.0 * a[1];
+            o[2 * nn + 2 * t] = -2.0 * a[0];
+            o[2 * nn + 2 * t + 1] = -2.0 * a[1];
+            break;
+        }
+        case V_F64: {
+            const double a = ((const double *)s)[e];
+            ((double *)d)[t] = 2.0 * a;
+            ((double *)d)[nn + t] = -2.0 * a;
+            break;
+        }
+        case V_MODP: {
+            const uint32_t p = md.p;
+            const uint32_t a = ((const uint32_t *)s)[e] % p;
+            const double b = a > p / 2 ? (double)a - (double)p : (double)a;
+            ((double *)d)[t] = 2.0 * b;
+            ((double *)d)[nn + t] = -2.0 * b;
+            break;
+        }
+        case V_MONT: {
+            const uint32_t p = md.p;
+            const uint32_t a = ((const uint32_t *)s)[e] % p;
+            const uint32_t two = (uint32_t)((2ull * a) % p);
+            uint32_t *o = (uint32_t *)d;
+            o[t] = two;
+            o[nn + t] = two ? p - two : 0u;
+            o[2 * nn + t] = a;
+            o[3 * nn + t] = a ? p - a : 0u;
+            break;
+        }
+        }
+    }
+}
+
+// ---------------------------------------------------------------- finalize
+__device__ uint64_t powmod_u64(uint64_t b, uint32_t e, uint64_t p)
+{
+    uint64_t r = 1 % p;
+    b %= p;
+    while (e) {
+        if (e & 1) r = (r * b) % p;
+        b = (b * b) % p;
+        e >>= 1;
+    }
+    return r;
+}
+
+__global__ __launch_bounds__(256) void finalize_kernel(const MatDesc *mats, const double *partials,
+                                                       char *out)
+{
+    __shared__ double sa[256], sb[256];
+    __shared__ unsigned long long su[256];
+    const MatDesc md = mats[blockIdx.x];
+    const int t = threadIdx.x;
+    const bool modp = md.variant == V_MODP || md.variant == V_MONT;
+    char *o = out + 16 * (size_t)md.out_slot;
+
+    if (md.num_parts == 0) {                // n = 0: the empty permanent is 1
+        if (t == 0) {
+            if (modp) {
+                ((uint32_t *)o)[0] = 1u % md.p;
+                ((uint32_t *)o)[1] = ((uint32_t *)o)[2] = ((uint32_t *)o)[3] = 0u;
+            } else {
+                ((double *)o)[0] = 1.0;
+                ((double *)o)[1] = 0.0;
+            }
+        }
+        return;
+    }
+    if (modp) {
+        const uint64_t P = md.p;
+        uint64_t acc = 0;
+        for (uint32_t q = t; q < md.num_parts; q += 256) {
+            acc += (uint64_t)partials[2 * ((size_t)md.first_part + q)];
+            if (acc >= (1ull << 62)) acc %= P;
+        }
+        su[t] = acc % P;
+        __syncthreads();
+        for (int w = 128; w >= 1; w >>= 1) {
+            if (t < w) su[t] = (su[t] + su[t + w]) % P;
+            __syncthreads();
+        }
+        if (t == 0) {
+            uint64_t v = su[0];
+            // Montgomery products leave R^{-(n-1)}; Glynn leaves 2^{n-1}.
+            uint64_t f = 1;
+            if (md.variant == V_MONT) f = powmod_u64((1ull << 32) % P, md.n - 1, P);
+            if (!(md.flags & MD_NO_SCALE)) f = (f * powmod_u64((P + 1) / 2, md.n - 1, P)) % P;
+            v = (v * f) % P;
+            ((uint32_t *)o)[0] = (uint32_t)v;
+            ((uint32_t *)o)[1] = ((uint32_t *)o)[2] = ((uint32_t *)o)[3] = 0u;
+        }
+        return;
+    }
+    // Floats: per-thread compensated sums over a fixed stride, then a fixed tree.
+    double s0 = 0.0, c0 = 0.0, s1 = 0.0, c1 = 0.0;
+    for (uint32_t q = t; q < md.num_parts; q += 256) {
+        const double *pp = partials + 2 * ((size_t)md.first_part + q);
+        kahan_add(s0, c0, pp[0]);
+        kahan_add(s1, c1, pp[1]);
+    }
+    sa[t] = s0 - c0;
+    sb[t] = s1 - c1;
+    __syncthreads();
+    for (int w = 128; w >= 1; w >>= 1) {
+        if (t < w) { sa[t] += sa[t + w]; sb[t] += sb[t + w]; }
+        __syncthreads();
+    }
+    if (t == 0) {
+        double a = sa[0], b = sb[0];
+        if (!(md.flags & MD_NO_SCALE)) {
+            a = __builtin_ldexp(a, -(md.n - 1));
+            b = __builtin_ldexp(b, -(md.n - 1));
+        }
+        ((double *)o)[0] = a;
+        ((double *)o)[1] = md.variant == V_C128 ? b : 0.0;
+    }
+}
+
+// ---------------------------------------------------------- host launchers
+static WalkFn fused_fn(int nmax, bool kahan)
+{
+    if (nmax <= 16) return kahan ? walk_fn_fused16_k() : walk_fn_fused16_nok();
+    if (nmax <= 26) return kahan ? walk_fn_fused26_k() : walk_fn_fused26_nok();
+    return nullptr;
+}
+
+static WalkFn pick(int variant, int n, bool kahan, bool fused, int nmax_fused)
+{
+    if (fused) return fused_fn(nmax_fused, kahan);
+    if (variant < 0 || variant >= V_COUNT || n < 1 || n > NMAX) return nullptr;
+    switch (variant) {
+    case V_C128: return n <= 24 ? walk_fn_c128_lo(n, kahan) : walk_fn_c128_hi(n, kahan);
+    case V_F64: return walk_fn_f64(n, kahan);
+    case V_MODP: return walk_fn_modp(n);
+    case V_MONT: return walk_fn_mont(n);
+    }
+    return nullptr;
+}
+
+int launch_stage(const MatDesc *d_mats, int nmats, const void *src, void *stage, void *stream)
+{
+    if (nmats <= 0) return (int)hipSuccess;
+    hipLaunchKernelGGL(stage_kernel, dim3(nmats), dim3(256), 0, (hipStream_t)stream, d_mats,
+                       (const char *)src, (char *)stage);
+    return (int)hipGetLastError();
+}
+
+int walk_occupancy(int variant, int n, bool kahan, bool fused, int nmax_fused, int *blocks_per_cu)
+{
+    WalkFn f = pick(variant, n, kahan, fused, nmax_fused);
+    if (!f) return (int)hipErrorInvalidValue;
+    int nb = 0;
+    hipError_t e = hipOccupancyMaxActiveBlocksPerMultiprocessor(&nb, (const void *)f, BLOCK, 0);
+    *blocks_per_cu = nb;
+    return (int)e;
+}
+
+int launch_walk(int variant, int n, bool kahan, bool fused, int nmax_fused, const WaveItem *d_items,
+                uint32_t count, const MatDesc *d_mats, const void *stage, double *partials,
+                unsigned long long *ctr, uint64_t base, int grid_blocks, void *stream,
+                uint64_t *ctr_advance)
+{
+    WalkFn f = pick(variant, n, kahan, fused, nmax_fused);
+    if (!f) return (int)hipErrorInvalidValue;
+    if (grid_blocks < 1) grid_blocks = 1;
+    const char *st = (const char *)stage;
+    void *args[] = {(void *)&d_items, (void *)&count, (void *)&d_mats, (void *)&st,
+                    (void *)&partials, (void *)&ctr, (void *)&base};
+    hipError_t e = hipLaunchKernel((const void *)f, dim3(grid_blocks), dim3(BLOCK), args, 0,
+                                   (hipStream_t)stream);
+    if (e != hipSuccess) return (int)e;
+    *ctr_advance = (uint64_t)count + (uint64_t)grid_blocks * (BLOCK / WAVE);
+    return (int)hipGetLastError();
+}
+
+int launch_finalize(const MatDesc *d_mats, int nmats, const double *partials, void *out, void *stream)
+{
+    if (nmats <= 0) return (int)hipSuccess;
+    hipLaunchKernelGGL(finalize_kernel, dim3(nmats), dim3(256), 0, (hipStream_t)stream, d_mats,
+                       partials, (char *)out);
+    return (int)hipGetLastError();
+}
+
+}  // namespace permk

@@ -1,0 +1,610 @@
+// Gray-code Glynn walk kernels for gfx950 (CDNA4, wave64).
+//
+// What is computed (paper Sec. 1 Note, Sec. 2.2-2.3; Glynn's formula): for an
+// n x n matrix A,
+//
+//   perm(A) = 2^{-(n-1)} * sum_{x=0}^{2^{n-1}-1} (-1)^x prod_{i<n} r_i(x),
+//   r_i(x)  = a_{i0} + sum_{k=1}^{n-1} d_k(x) a_{ik},
+//   d_k(x)  = 1 - 2 * bit_{k-1}(gray(x)),   gray(x) = x XOR (x >> 1).
+//
+// Going from x-1 to x flips gray bit b = ctz(x), i.e. column k = b + 1: all n
+// row sums move by -2 a_{ik} when that bit turns on and by +2 a_{ik} when it
+// turns off.  The product of the d_k equals (-1)^x.
+//
+// Work split (the paper's contiguous Gray-code blocks, Sec. 2.2): a wave item
+// is 64 lanes, lane l walking the 2^c consecutive indices starting at
+// x_l = x0 + l * 2^c with x0 a multiple of 2^c.  Because every x_l is aligned,
+// at step j (0 < j < 2^c) all lanes flip the same column ctz(j)+1 in the same
+// direction, except at j = 2^{c-1}, where the direction depends on bit c of
+// x_l.  So the flip column is wave-uniform: the staging kernel stores +2A and
+// -2A column by column, the walk picks the column with scalar arithmetic,
+// reads it with scalar loads (s_load into SGPRs) and adds it to the per-lane
+// row sums held in VGPRs (v_add_f64 with an SGPR operand): a flip is n adds
+// and no branch.
+//
+// Per step each lane does: n adds (flip), an n-way product (four interleaved
+// chains, then a fixed combining tree), and one signed accumulate.
+//
+//   V_C128  complex row sums; complex products with FMA; Kahan-compensated
+//           sums of the real and imaginary parts (paper Sec. 1 Note).
+//   V_F64   the same over R.
+//   V_MODP  F_p with p < 2^31 odd.  Entries are taken as balanced residues
+//           |a| <= (p-1)/2, so every row sum is an exact integer of magnitude
+//           below n*p/2 < 2^36 and is never reduced.  Products are reduced by
+//           an exact Barrett step in binary64: h = a*b rounded, l = fma(a,b,-h)
+//           (the exact rounding error), q = rint(h * (1/p)), d = fma(-q,p,h)
+//           (exact), result d + l, exactly congruent to a*b and of magnitude
+//           below p.  The signed sum of a lane is an exact integer below 2^52.
+//   V_MONT  F_p with uint32 residues in [0,p) and 32-bit Montgomery products
+//           (R = 2^32); the n-1 products leave a factor R^{-(n-1)} that the
+//           finalize step removes.
+//
+// Reduction: lane sums -> xor-butterfly across the wave -> one partial per
+// wave item -> per matrix, a fixed-order block reduction in finalize.  No
+// atomics touch the values, so results are bit-reproducible for a fixed
+// partition of [0, 2^{n-1}).
+#pragma once
+#include <hip/hip_runtime.h>
+#include <stdint.h>
+#include <utility>
+
+#include "kernels.h"
+
+namespace permk {
+
+template <typename T>
+using sptr = const __attribute__((address_space(4))) T *;
+
+template <typename T>
+__device__ __forceinline__ sptr<T> sp(const void *p)
+{
+    return (sptr<T>)(p);
+}
+
+// Copy a descriptor with scalar loads (the struct is uniform across the wave).
+template <typename T>
+__device__ __forceinline__ T sload(const T *p)
+{
+    static_assert(sizeof(T) % 8 == 0, "descriptor size");
+    uint64_t w[sizeof(T) / 8];
+    sptr<uint64_t> q = sp<uint64_t>(p);
+#pragma unroll
+    for (int i = 0; i < (int)(sizeof(T) / 8); ++i) w[i] = q[i];
+    T out;
+    __builtin_memcpy(&out, w, sizeof(T));
+    return out;
+}
+
+// Hide a uniform pointer's provenance so that column loads stay inside the
+// loop iteration that uses them (hoisting whole columns out of the loop would
+// overflow the SGPR file).
+__device__ __forceinline__ const char *opaque(const char *p)
+{
+    asm volatile("" : "+s"(p));
+    return p;
+}
+
+__device__ __forceinline__ void kahan_add(double &s, double &c, double v)
+{
+    const double y = v - c;
+    const double t = s + y;
+    c = (t - s) - y;
+    s = t;
+}
+
+__device__ __forceinline__ void cmul(double &ar, double &ai, double br, double bi)
+{
+    const double r = __builtin_fma(ar, br, -(ai * bi));
+    const double i = __builtin_fma(ar, bi, ai * br);
+    ar = r;
+    ai = i;
+}
+
+// Exact a*b mod p as a balanced value, for integers |a|,|b| < 2^36, p < 2^31.
+__device__ __forceinline__ double mulmod_f64(double a, double b, double p, double pinv)
+{
+    const double h = a * b;
+    const double l = __builtin_fma(a, b, -h);
+    const double q = __builtin_rint(h * pinv);
+    const double d = __builtin_fma(-q, p, h);
+    return d + l;
+}
+
+__device__ __forceinline__ uint32_t montmul(uint32_t a, uint32_t b, uint32_t p, uint32_t pp)
+{
+    const uint64_t t = (uint64_t)a * b;
+    const uint32_t m = (uint32_t)t * pp;
+    const uint64_t u = (t + (uint64_t)m * p) >> 32;      // < 2p
+    const uint32_t r = (uint32_t)u;
+    return min(r, r - p);
+}
+
+__device__ __forceinline__ uint32_t addmod(uint32_t a, uint32_t b, uint32_t p)
+{
+    const uint32_t s = a + b;                            // a, b < p < 2^31
+    return min(s, s - p);
+}
+
+// Number of interleaved product chains.
+template <int N>
+struct Chains {
+    static constexpr int K = N < 4 ? N : 4;
+};
+
+// Row sums as binary64 values, common to the c128, f64 and F_p (Barrett)
+// variants.  E = doubles per entry (2 for complex, 1 for real).  The staged
+// buffer holds [+2A columns][-2A columns], each column n*E doubles.
+template <int N, int E>
+struct RealRows {
+    double r[N * E];
+    const char *cols;
+
+    __device__ __forceinline__ sptr<double> col(int k, bool neg) const
+    {
+        return sp<double>(cols) + (neg ? N * N * E : 0) + N * E * k;
+    }
+    __device__ __forceinline__ void seed(uint64_t x)
+    {
+        const uint64_t g = x ^ (x >> 1);
+        sptr<double> c0 = col(0, false);
+#pragma unroll
+        for (int i = 0; i < N * E; ++i) r[i] = c0[i];
+#pragma unroll 1
+        for (int k = 1; k < N; ++k) {
+            const double d = ((g >> (k - 1)) & 1) ? -1.0 : 1.0;
+            sptr<double> ck = col(k, false);
+#pragma unroll
+            for (int i = 0; i < N * E; ++i) r[i] = __builtin_fma(d, ck[i], r[i]);
+        }
+#pragma unroll
+        for (int i = 0; i < N * E; ++i) r[i] *= 0.5;
+    }
+    __device__ __forceinline__ void flip(sptr<double> c)
+    {
+#pragma unroll
+        for (int i = 0; i < N * E; ++i) r[i] += c[i];
+    }
+    __device__ __forceinline__ void flip_lane(int k, bool up)
+    {
+        const double s = up ? 1.0 : -1.0;
+        sptr<double> c = col(k, false);
+#pragma unroll
+        for (int i = 0; i < N * E; ++i) r[i] = __builtin_fma(s, c[i], r[i]);
+    }
+};
+
+// ------------------------------------------------------------------- C128
+template <int N, bool KAHAN>
+struct OpsC128 : RealRows<N, 2> {
+    using RealRows<N, 2>::r;
+    double sr, si, cr, ci;
+
+    __device__ __forceinline__ void setup(const MatDesc &, const char *c)
+    {
+        this->cols = c;
+        sr = si = cr = ci = 0.0;
+    }
+    __device__ __forceinline__ void product(double &pr, double &pi) const
+    {
+        constexpr int K = Chains<N>::K;
+        double ar[K], ai[K];
+#pragma unroll
+        for (int c = 0; c < K; ++c) { ar[c] = r[2 * c]; ai[c] = r[2 * c + 1]; }
+#pragma unroll
+        for (int i = K; i < N; ++i) cmul(ar[i % K], ai[i % K], r[2 * i], r[2 * i + 1]);
+#pragma unroll
+        for (int w = 1; w < K; w *= 2)
+#pragma unroll
+            for (int c = 0; c + w < K; c += 2 * w) cmul(ar[c], ai[c], ar[c + w], ai[c + w]);
+        pr = ar[0];
+        pi = ai[0];
+    }
+    __device__ __forceinline__ void acc(double pr, double pi)
+    {
+        if (KAHAN) { kahan_add(sr, cr, pr); kahan_add(si, ci, pi); }
+        else { sr += pr; si += pi; }
+    }
+    template <bool NEG>
+    __device__ __forceinline__ void term()
+    {
+        double pr, pi;
+        product(pr, pi);
+        if (NEG) acc(-pr, -pi); else acc(pr, pi);
+    }
+    __device__ __forceinline__ void term_lane(bool neg)
+    {
+        double pr, pi;
+        product(pr, pi);
+        const double s = neg ? -1.0 : 1.0;
+        acc(s * pr, s * pi);
+    }
+    __device__ __forceinline__ void result(double &a, double &b) const
+    {
+        a = KAHAN ? sr - cr : sr;
+        b = KAHAN ? si - ci : si;
+    }
+    __device__ __forceinline__ void store(double *part, double a, double b) const
+    {
+        part[0] = a;
+        part[1] = b;
+    }
+};
+
+// -------------------------------------------------------------------- F64
+template <int N, bool KAHAN>
+struct OpsF64 : RealRows<N, 1> {
+    using RealRows<N, 1>::r;
+    double s, c;
+
+    __device__ __forceinline__ void setup(const MatDesc &, const char *cc)
+    {
+        this->cols = cc;
+        s = c = 0.0;
+    }
+    __device__ __forceinline__ double product() const
+    {
+        constexpr int K = Chains<N>::K;
+        double a[K];
+#pragma unroll
+        for (int q = 0; q < K; ++q) a[q] = r[q];
+#pragma unroll
+        for (int i = K; i < N; ++i) a[i % K] *= r[i];
+#pragma unroll
+        for (int w = 1; w < K; w *= 2)
+#pragma unroll
+            for (int q = 0; q + w < K; q += 2 * w) a[q] *= a[q + w];
+        return a[0];
+    }
+    __device__ __forceinline__ void acc(double v)
+    {
+        if (KAHAN) kahan_add(s, c, v); else s += v;
+    }
+    template <bool NEG>
+    __device__ __forceinline__ void term()
+    {
+        const double v = product();
+        acc(NEG ? -v : v);
+    }
+    __device__ __forceinline__ void term_lane(bool neg)
+    {
+        const double v = product();
+        acc(neg ? -v : v);
+    }
+    __device__ __forceinline__ void result(double &a, double &b) const
+    {
+        a = KAHAN ? s - c : s;
+        b = 0.0;
+    }
+    __device__ __forceinline__ void store(double *part, double a, double) const
+    {
+        part[0] = a;
+        part[1] = 0.0;
+    }
+};
+
+// ------------------------------------------------------ F_p, FP64 Barrett
+__device__ __forceinline__ double reduce_to_range(double v, double p, double pinv)
+{
+    // v an integer with |v| < 2^52: return v mod p in [0, p)
+    const double q = __builtin_rint(v * pinv);
+    double r = __builtin_fma(-q, p, v);
+    if (r < 0.0) r += p;
+    if (r >= p) r -= p;
+    return r;
+}
+
+template <int N>
+struct OpsModp : RealRows<N, 1> {
+    using RealRows<N, 1>::r;
+    double s;
+    double p, pinv;
+
+    __device__ __forceinline__ void setup(const MatDesc &md, const char *cc)
+    {
+        this->cols = cc;
+        s = 0.0;
+        p = (double)md.p;
+        pinv = md.pinv;
+    }
+    __device__ __forceinline__ double product() const
+    {
+        constexpr int K = Chains<N>::K;
+        double a[K];
+#pragma unroll
+        for (int q = 0; q < K; ++q) a[q] = r[q];
+#pragma unroll
+        for (int i = K; i < N; ++i) a[i % K] = mulmod_f64(a[i % K], r[i], p, pinv);
+#pragma unroll
+        for (int w = 1; w < K; w *= 2)
+#pragma unroll
+            for (int q = 0; q + w < K; q += 2 * w) a[q] = mulmod_f64(a[q], a[q + w], p, pinv);
+        return a[0];
+    }
+    template <bool NEG>
+    __device__ __forceinline__ void term()
+    {
+        const double v = product();
+        s = NEG ? s - v : s + v;
+    }
+    __device__ __forceinline__ void term_lane(bool neg)
+    {
+        const double v = product();
+        s = neg ? s - v : s + v;
+    }
+    __device__ __forceinline__ void result(double &a, double &b) const
+    {
+        // For N == 1 the "product" is the unreduced row sum itself.
+        a = reduce_to_range(s, p, pinv);
+        b = 0.0;
+    }
+    __device__ __forceinline__ void store(double *part, double a, double) const
+    {
+        part[0] = reduce_to_range(a, p, pinv);     // wave sum < 64 p
+        part[1] = 0.0;
+    }
+};
+
+// ------------------------------------------------- F_p, 32-bit Montgomery
+template <int N>
+struct OpsMont {
+    uint32_t r[N];
+    uint64_t spos, sneg;
+    uint32_t p, pp;
+    const char *cols;
+
+    __device__ __forceinline__ void setup(const MatDesc &md, const char *cc)
+    {
+        cols = cc;
+        spos = sneg = 0;
+        p = md.p;
+        pp = md.mont_pp;
+    }
+    // staged arrays: [2a mod p][(p - 2a) mod p][a][(p - a) mod p], column-major
+    __device__ __forceinline__ sptr<uint32_t> col(int k, bool neg) const
+    {
+        return sp<uint32_t>(cols) + (neg ? N * N : 0) + N * k;
+    }
+    __device__ __forceinline__ sptr<uint32_t> aval(int k, bool neg) const
+    {
+        return sp<uint32_t>(cols) + (neg ? 3 * N * N : 2 * N * N) + N * k;
+    }
+    __device__ __forceinline__ void seed(uint64_t x)
+    {
+        const uint64_t g = x ^ (x >> 1);
+        sptr<uint32_t> c0 = aval(0, false);
+#pragma unroll
+        for (int i = 0; i < N; ++i) r[i] = c0[i];
+#pragma unroll 1
+        for (int k = 1; k < N; ++k) {
+            const bool neg = (g >> (k - 1)) & 1;
+            sptr<uint32_t> ca = aval(k, false);
+            sptr<uint32_t> cn = aval(k, true);
+#pragma unroll
+            for (int i = 0; i < N; ++i) r[i] = addmod(r[i], neg ? cn[i] : ca[i], p);
+        }
+    }
+    __device__ __forceinline__ void flip(sptr<uint32_t> c)
+    {
+#pragma unroll
+        for (int i = 0; i < N; ++i) r[i] = addmod(r[i], c[i], p);
+    }
+    __device__ __forceinline__ void flip_lane(int k, bool up)
+    {
+        sptr<uint32_t> cp = col(k, false);
+        sptr<uint32_t> cm = col(k, true);
+#pragma unroll
+        for (int i = 0; i < N; ++i) r[i] = addmod(r[i], up ? cp[i] : cm[i], p);
+    }
+    __device__ __forceinline__ uint32_t product() const
+    {
+        constexpr int K = Chains<N>::K;
+        uint32_t a[K];
+#pragma unroll
+        for (int q = 0; q < K; ++q) a[q] = r[q];
+#pragma unroll
+        for (int i = K; i < N; ++i) a[i % K] = montmul(a[i % K], r[i], p, pp);
+#pragma unroll
+        for (int w = 1; w < K; w *= 2)
+#pragma unroll
+            for (int q = 0; q + w < K; q += 2 * w) a[q] = montmul(a[q], a[q + w], p, pp);
+        return a[0];
+    }
+    template <bool NEG>
+    __device__ __forceinline__ void term()
+    {
+        const uint32_t v = product();
+        if (NEG) sneg += v; else spos += v;
+    }
+    __device__ __forceinline__ void term_lane(bool neg)
+    {
+        const uint32_t v = product();
+        spos += neg ? 0u : v;
+        sneg += neg ? v : 0u;
+    }
+    __device__ __forceinline__ void result(double &a, double &b) const
+    {
+        const uint64_t P = p;
+        a = (double)((spos % P + P - sneg % P) % P);
+        b = 0.0;
+    }
+    __device__ __forceinline__ void store(double *part, double a, double) const
+    {
+        part[0] = (double)((uint64_t)a % (uint64_t)p);
+        part[1] = 0.0;
+    }
+};
+
+template <int V, int N, bool K> struct OpsFor;
+template <int N, bool K> struct OpsFor<V_C128, N, K> { using type = OpsC128<N, K>; };
+template <int N, bool K> struct OpsFor<V_F64, N, K> { using type = OpsF64<N, K>; };
+template <int N, bool K> struct OpsFor<V_MODP, N, K> { using type = OpsModp<N>; };
+template <int N, bool K> struct OpsFor<V_MONT, N, K> { using type = OpsMont<N>; };
+
+// ------------------------------------------------------------- the walk
+// Steps j = 4m .. 4m+3 of a lane's chunk (m > 0, j != L/2).  Steps 4m+1 and
+// 4m+3 flip column 1 (down, then up); step 4m+2 flips column 2, down for even
+// m and up for odd m; step 4m flips column b+1 with b = ctz(4m), up exactly
+// when bit b+1 of j is set.
+template <class Ops>
+__device__ __forceinline__ void group_tail(Ops &S, uint32_t m)
+{
+    S.template term<false>();
+    S.flip(S.col(1, true));
+    S.template term<true>();
+    S.flip(S.col(2, !(m & 1)));
+    S.template term<false>();
+    S.flip(S.col(1, false));
+    S.template term<true>();
+}
+
+template <class Ops>
+__device__ __forceinline__ void group(Ops &S, const char *cols, uint32_t m)
+{
+    S.cols = opaque(cols);
+    const uint32_t j = m << 2;
+    const uint32_t b = __builtin_ctz(j);
+    S.flip(S.col(b + 1, !((j >> (b + 1)) & 1)));
+    group_tail(S, m);
+}
+
+// One lane: seed at xl, then the 2^c - 1 Gray steps of its chunk.
+template <class Ops>
+__device__ __forceinline__ void walk_lane(Ops &S, uint64_t xl, uint32_t c)
+{
+    const char *cols = S.cols;
+    S.seed(xl);
+    if (c >= 3) {
+        const uint32_t G = 1u << (c - 2);      // groups of four steps
+        const uint32_t H = G >> 1;             // the group holding j = L/2
+        group_tail(S, 0);
+#pragma unroll 1
+        for (uint32_t m = 1; m < H; ++m) group(S, cols, m);
+        // j = L/2: column c, direction from bit c of the lane's start index.
+        S.cols = opaque(cols);
+        S.flip_lane(c, (xl >> c) & 1);
+        group_tail(S, H);
+#pragma unroll 1
+        for (uint32_t m = H + 1; m < G; ++m) group(S, cols, m);
+    } else {
+        // Chunks of 1, 2 or 4 indices (tiny matrices, range ends): take the
+        // direction and sign of every step from the lane's own index.
+        S.term_lane(xl & 1);
+#pragma unroll 1
+        for (uint32_t j = 1; j < (1u << c); ++j) {
+            const uint32_t b = __builtin_ctz(j);
+            const uint64_t x = xl + j;
+            S.flip_lane(b + 1, (x >> (b + 1)) & 1);
+            S.term_lane(x & 1);
+        }
+    }
+}
+
+__device__ __forceinline__ double wave_sum(double v)
+{
+#pragma unroll
+    for (int off = 32; off >= 1; off >>= 1) v += __shfl_xor(v, off, WAVE);
+    return v;
+}
+
+template <class Ops>
+__device__ __forceinline__ void run_item(const WaveItem &it, const MatDesc &md, const char *stage,
+                                         double *partials, int lane)
+{
+    Ops S;
+    S.setup(md, stage + md.stage_off);
+    const uint64_t xl = it.x0 + ((uint64_t)lane << it.log2L);
+    walk_lane(S, xl, it.log2L);
+    double a, b;
+    S.result(a, b);
+    if ((uint32_t)lane >= it.nlanes) { a = 0.0; b = 0.0; }
+    a = wave_sum(a);
+    b = wave_sum(b);
+    if (lane == 0) S.store(partials + 2 * (size_t)it.slot, a, b);
+}
+
+// Fetch the next wave item index, uniform across the wave.  Every lane
+// executes the atomic (lane 0 adds 1, the others 0) so that no divergent
+// branch precedes the readfirstlane: with the add under `if (lane == 0)` the
+// compiler may thread that branch into the loop's other lane-0 branch and
+// leave lanes 1..63 in a loop that re-reads a stale index.
+__device__ __forceinline__ uint32_t next_item(unsigned long long *ctr, uint64_t base, int lane)
+{
+    const unsigned long long got = atomicAdd(ctr, lane == 0 ? 1ull : 0ull);
+    const uint32_t lo = __builtin_amdgcn_readfirstlane((uint32_t)(got - base));
+    return lo;
+}
+
+// Persistent kernel: every wave pulls wave items (largest first, as ordered
+// by the host) until the counter passes `count`.
+template <int V, int N, bool KAHAN>
+__global__ __launch_bounds__(BLOCK) void walk_kernel(const WaveItem *items, uint32_t count,
+                                                     const MatDesc *mats, const char *stage,
+                                                     double *partials, unsigned long long *ctr,
+                                                     uint64_t base)
+{
+    const int lane = threadIdx.x & (WAVE - 1);
+    for (uint32_t idx = next_item(ctr, base, lane); idx < count; idx = next_item(ctr, base, lane)) {
+        const WaveItem it = sload(items + idx);
+        const MatDesc md = sload(mats + it.mat);
+        run_item<typename OpsFor<V, N, KAHAN>::type>(it, md, stage, partials, lane);
+    }
+}
+
+// Fused kernel: any mix of c128 / f64 / F_p (Barrett) matrices of order <= NF.
+template <int N, bool KAHAN>
+__device__ __forceinline__ void run_variant(int v, const WaveItem &it, const MatDesc &md,
+                                            const char *stage, double *partials, int lane)
+{
+    if (v == V_C128) run_item<OpsC128<N, KAHAN>>(it, md, stage, partials, lane);
+    else if (v == V_F64) run_item<OpsF64<N, KAHAN>>(it, md, stage, partials, lane);
+    else run_item<OpsModp<N>>(it, md, stage, partials, lane);
+}
+
+template <bool KAHAN, int... Ns>
+__device__ __forceinline__ void run_fused(std::integer_sequence<int, Ns...>, int n, int v,
+                                          const WaveItem &it, const MatDesc &md, const char *stage,
+                                          double *partials, int lane)
+{
+    (void)((n == Ns + 1 ? (run_variant<Ns + 1, KAHAN>(v, it, md, stage, partials, lane), true)
+                        : false) || ...);
+}
+
+template <int NF, bool KAHAN>
+__global__ __launch_bounds__(BLOCK) void walk_fused(const WaveItem *items, uint32_t count,
+                                                    const MatDesc *mats, const char *stage,
+                                                    double *partials, unsigned long long *ctr,
+                                                    uint64_t base)
+{
+    const int lane = threadIdx.x & (WAVE - 1);
+    for (uint32_t idx = next_item(ctr, base, lane); idx < count; idx = next_item(ctr, base, lane)) {
+        const WaveItem it = sload(items + idx);
+        const MatDesc md = sload(mats + it.mat);
+        run_fused<KAHAN>(std::make_integer_sequence<int, NF>{}, md.n, md.variant, it, md, stage,
+                         partials, lane);
+    }
+}
+
+// ------------------------------------------------ instantiation tables
+using WalkFn = void (*)(const WaveItem *, uint32_t, const MatDesc *, const char *, double *,
+                        unsigned long long *, uint64_t);
+
+template <int V, bool K, int LO, int... Ns>
+inline WalkFn walk_fn_range(int n, std::integer_sequence<int, Ns...>)
+{
+    static const WalkFn tab[] = {&walk_kernel<V, LO + Ns, K>...};
+    const int i = n - LO;
+    return (i >= 0 && i < (int)sizeof...(Ns)) ? tab[i] : nullptr;
+}
+
+// Defined in the walk_inst_*.hip translation units (compiled in parallel).
+WalkFn walk_fn_c128_lo(int n, bool kahan);   // n = 1..24
+WalkFn walk_fn_c128_hi(int n, bool kahan);   // n = 25..48
+WalkFn walk_fn_f64(int n, bool kahan);
+WalkFn walk_fn_modp(int n);
+WalkFn walk_fn_mont(int n);
+WalkFn walk_fn_fused16_k();
+WalkFn walk_fn_fused16_nok();
+WalkFn walk_fn_fused26_k();
+WalkFn walk_fn_fused26_nok();
+
+}  // namespace permk

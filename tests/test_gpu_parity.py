@@ -1,0 +1,223 @@
+"""GPU parity: the HIP path against the oracle, element by element.
+
+Floats: |perm_gpu - perm_oracle| <= 1e-10 * prod_i ||row_i||_2 (complex
+modulus for c128).  F_p and CRT: bit-exact.  Sizes are those the oracle
+finishes in seconds; they span several wave items and the short-chunk paths.
+"""
+import math
+
+import numpy as np
+import pytest
+
+from paper_2602_10141_amd import ensembles as E
+
+pytestmark = pytest.mark.gpu
+
+TOL = 1e-10
+
+
+@pytest.fixture(scope="module")
+def P():
+    import torch
+    if not torch.cuda.is_available():
+        pytest.fail("no GPU visible")
+    from paper_2602_10141_amd import perm
+    return perm
+
+
+@pytest.fixture(scope="module")
+def ctx(P):
+    c = P.Context(0)
+    yield c
+    c.close()
+
+
+@pytest.fixture(scope="module")
+def O(oracle_lib):
+    return oracle_lib
+
+
+def scale(A):
+    return max(float(np.prod(np.linalg.norm(A, axis=1))), 1e-300) if len(A) else 1.0
+
+
+# ----------------------------------------------------------- single matrices
+@pytest.mark.parametrize("n", list(range(0, 13)) + [14, 16, 18, 20])
+def test_c128_random(P, ctx, O, n):
+    A = E.ginibre_complex(n, E.rng(1, n)) if n else np.zeros((0, 0), complex)
+    got = P.perm_c128(ctx, A)
+    want = O.native.ryser_c128(A) if n else 1.0
+    assert abs(got - want) <= TOL * scale(A), (got, want)
+
+
+@pytest.mark.parametrize("n", list(range(0, 13)) + [15, 17, 21])
+def test_f64_random(P, ctx, O, n):
+    A = E.ginibre_real(n, E.rng(2, n)) if n else np.zeros((0, 0))
+    got = P.perm_f64(ctx, A)
+    want = O.native.ryser_f64(A) if n else 1.0
+    assert abs(got - want) <= TOL * scale(A), (got, want)
+
+
+@pytest.mark.parametrize("p", [3, 5, 97, 65537, 1073742209, 2147483647])
+@pytest.mark.parametrize("n", [0, 1, 2, 3, 5, 7, 8, 9, 11, 13, 16, 19])
+@pytest.mark.parametrize("mont", [False, True])
+def test_modp_random(P, ctx, O, n, p, mont):
+    A = E.random_residues(n, p, E.rng(3, n * 7 + p % 101)) if n else np.zeros((0, 0), np.uint32)
+    got = P.perm_modp(ctx, A, p, flags=P.PERM_MONTGOMERY if mont else 0)
+    want = O.native.ryser_modp(A, p) if n else 1 % p
+    assert got == want
+
+
+def test_modp_entries_reduced(P, ctx, O):
+    """Entries >= p are taken mod p."""
+    p, n = 101, 9
+    A = E.random_residues(n, 2 ** 31 - 1, E.rng(4, 0))
+    assert P.perm_modp(ctx, A, p) == O.native.ryser_modp(A % p, p)
+
+
+def test_config1_haar_unitary_14(P, ctx, O):
+    """Single 14x14 complex128 Haar unitary (QR of CN(0,1) Ginibre, phases folded)."""
+    U = E.haar_unitary(14, E.rng(1, 0))
+    got = P.perm_c128(ctx, U)
+    want = O.native.ryser_c128(U)
+    assert abs(got - want) <= TOL * scale(U)
+    assert abs(got) <= 1 + 1e-12
+
+
+def test_device_pointer_path(P, ctx, O):
+    import torch
+    A = E.ginibre_complex(13, E.rng(5, 0))
+    out = P.perm_c128(ctx, torch.from_numpy(A).cuda())
+    torch.cuda.synchronize()
+    got = complex(*out.cpu().numpy())
+    assert abs(got - O.native.ryser_c128(A)) <= TOL * scale(A)
+    R = E.random_residues(12, 1073742209, E.rng(5, 1))
+    o = P.perm_modp(ctx, torch.from_numpy(R.astype(np.int32)).cuda(), 1073742209)
+    torch.cuda.synchronize()
+    assert int(o.cpu()[0]) == O.native.ryser_modp(R, 1073742209)
+
+
+def test_kahan_off_still_within_tolerance(P, ctx, O):
+    A = E.ginibre_complex(16, E.rng(6, 0))
+    got = P.perm_c128(ctx, A, flags=P.PERM_NO_KAHAN)
+    assert abs(got - O.native.ryser_c128(A)) <= TOL * scale(A)
+
+
+def test_repeat_bit_identical(P, ctx):
+    A = E.ginibre_complex(18, E.rng(7, 0))
+    vals = {P.perm_c128(ctx, A) for _ in range(3)}
+    assert len(vals) == 1
+
+
+# ------------------------------------------------------------------- Schur
+@pytest.mark.parametrize("n", [3, 5, 7, 9, 10, 11, 13, 15, 17, 19, 21])
+def test_schur_modp(P, ctx, O, n):
+    for p in O.crt.primes_1_mod_n(n, 2):
+        S_lib = P.perm_schur_residues(n, p)
+        S_or = O.crt.schur_residues(n, p)
+        assert np.array_equal(S_lib, S_or)
+        want = O.native.ryser_modp(S_or, p)
+        assert P.perm_modp(ctx, S_lib, p) == want
+        if n % 2 == 0:
+            assert want == 0
+
+
+@pytest.mark.parametrize("n", [5, 7, 9, 11, 13])
+def test_schur_crt_exact(P, ctx, O, n):
+    primes = P.perm_schur_primes(n)
+    assert primes == O.crt.primes_for_schur(n)
+    mats = np.stack([P.perm_schur_residues(n, p) for p in primes])
+    val, res = P.perm_crt_int(ctx, mats, primes, (n / 2) * math.log2(n))
+    want_res = [O.native.ryser_modp(m, p) for m, p in zip(mats, primes)]
+    assert res == want_res
+    assert val == O.crt.crt_lift(want_res, primes)
+    if n <= 10:
+        assert val == O.crt.schur_perm_exact(n)
+
+
+def test_crt_factorial_sign(P, ctx, O):
+    n = 21
+    primes = O.crt.primes_1_mod_n(2, 3)
+    J = np.stack([np.ones((n, n), np.uint32)] * 3)
+    val, _ = P.perm_crt_int(ctx, J, primes, math.log2(math.factorial(n)) + 1)
+    assert val == math.factorial(n)
+    Jm = J.copy()
+    for i, p in enumerate(primes):
+        Jm[i, 0, :] = p - 1
+    val, _ = P.perm_crt_int(ctx, Jm, primes, math.log2(math.factorial(n)) + 1)
+    assert val == -math.factorial(n)
+
+
+# ------------------------------------------------------------------- ranges
+@pytest.mark.parametrize("field", ["c128", "f64", "modp"])
+def test_range_partials(P, ctx, O, field):
+    n = 14
+    T = 1 << (n - 1)
+    g = E.rng(8, 0)
+    if field == "c128":
+        A = E.ginibre_complex(n, g)
+    elif field == "f64":
+        A = E.ginibre_real(n, g)
+    else:
+        A = E.random_residues(n, 1073742209, g)
+    items, data = P.pack_matrices([(A, field, 1073742209 if field == "modp" else 0)])
+    for x0, x1 in [(0, T), (1, 2), (3, 77), (100, 4100), (T - 5, T), (0, 1), (4096, 8192), (7, 7)]:
+        got = P.perm_range(ctx, items[0], data, x0, x1)
+        if field == "c128":
+            want = O.native.glynn_range_c128(A, x0, x1)
+            assert abs(got - want) <= TOL * scale(A) * max(1, x1 - x0) ** 0.5
+        elif field == "f64":
+            want = O.native.glynn_range_f64(A, x0, x1)
+            assert abs(got - want) <= TOL * scale(A) * max(1, x1 - x0) ** 0.5
+        else:
+            assert got == O.native.glynn_range_modp(A, 1073742209, x0, x1)
+
+
+def test_range_rejects_bad_bounds(P, ctx):
+    items, data = P.pack_matrices([(np.eye(5), "f64", 0)])
+    with pytest.raises(P.PermError) as e:
+        P.perm_range(ctx, items[0], data, 3, 17)
+    assert e.value.status == P.PERM_EINVAL
+
+
+# -------------------------------------------------------------------- batch
+def test_batch_mixed_matches_single_bitwise(P, ctx, O):
+    g = E.rng(9, 0)
+    mats = []
+    for n in [0, 1, 2, 5, 8, 11, 13, 16, 20, 24, 3]:
+        mats.append((E.ginibre_complex(n, g) if n else np.zeros((0, 0), complex), "c128", 0))
+        mats.append((E.ginibre_real(n, g) if n else np.zeros((0, 0)), "f64", 0))
+        mats.append((E.random_residues(n, 65537, g), "modp", 65537))
+    items, data = P.pack_matrices(mats)
+    out = P.perm_batch(ctx, items, data)
+    vals = P.batch_values(items, out)
+    for (A, field, p), v in zip(mats, vals):
+        n = A.shape[0]
+        if field == "c128":
+            single = P.perm_c128(ctx, A)
+            assert v == single
+            if n <= 16:
+                assert abs(v - (O.native.ryser_c128(A) if n else 1)) <= TOL * scale(A)
+        elif field == "f64":
+            single = P.perm_f64(ctx, A)
+            assert v == single
+            if n <= 16:
+                assert abs(v - (O.native.ryser_f64(A) if n else 1)) <= TOL * scale(A)
+        else:
+            assert v == P.perm_modp(ctx, A, p)
+            if n <= 16:
+                assert v == (O.native.ryser_modp(A, p) if n else 1)
+
+
+def test_batch_device_path_and_bad_item(P, ctx):
+    import torch
+    mats = [(E.ginibre_complex(10, E.rng(10, i)), "c128", 0) for i in range(5)]
+    items, data = P.pack_matrices(mats)
+    out = P.perm_batch(ctx, items, torch.from_numpy(data).cuda())
+    torch.cuda.synchronize()
+    host = P.perm_batch(ctx, items, data)
+    assert np.array_equal(out.cpu().numpy(), host)
+    items["n"][2] = 60
+    with pytest.raises(P.PermError) as e:
+        P.perm_batch(ctx, items, data)
+    assert e.value.status == P.PERM_EINVAL and "item 2" in str(e.value)
