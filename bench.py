@@ -1,0 +1,304 @@
+"""Benchmark of the Gray-code Glynn permanent path on one MI355X.
+
+Default workload (one "step" = the whole hot path once): the exact integer
+permanent of the Schur matrix S_28 by CRT over the three smallest 31-bit
+primes p = 1 (mod 28) -- per prime the residue matrix (g^{jk} mod p) already
+resident in HBM, then stage, Gray-code walk over 2^27 Glynn terms, fixed-order
+reduction and 2^-(27) scaling on the device, then the Garner lift on the host.
+Throughput is Glynn subset-terms per second (2^(n-1) per permanent).
+
+Other workloads (--workload): single14 (one 14x14 Haar unitary, c128),
+haar20 (50,000 Haar U(20) c128 and 50,000 Haar O(20) f64 in one persistent
+launch each), ragged (10,000 GUE/GOE/real and complex Ginibre matrices,
+n uniform in 8..24, one fused launch), serve (Poisson-arrival geodesic and
+Schur requests through the request loop; p50/p99 latency).
+
+Prints one JSON line.  The oracle (CPU Ryser) is timed on a bounded prefix of
+the same computation for the "cpu_baseline" field.
+"""
+import argparse
+import json
+import math
+import os
+import sys
+import threading
+import time
+
+ROOT = os.path.dirname(os.path.abspath(__file__))
+sys.path.insert(0, ROOT)
+
+import numpy as np  # noqa: E402
+
+METRIC = "Ryser subset-terms/s (c128, F_p) n=20–36; batched perms/s; served p50/p99"
+PEAK_LANE_OPS = 256 * 4 * 16 * 2.4e9        # FP64 VALU lane-ops/s: 256 CUs x 4 SIMD16 x 2.4 GHz
+PEAK_FP64_FLOPS = 78.6e12                    # FMA counted twice
+HOST_THREADS = 16                            # CPU share of one GPU on the box
+
+
+def ops_per_term(field: str, n: int, kahan: bool = True) -> int:
+    """Algorithmic FP64 VALU instructions per Glynn term (one lane, one step)."""
+    if field == "c128":        # 2n flip adds + 4(n-1) complex-product ops + Kahan
+        return 2 * n + 4 * (n - 1) + (8 if kahan else 2)
+    if field == "f64":         # n flip adds + (n-1) products + Kahan
+        return n + (n - 1) + (4 if kahan else 1)
+    # F_p, exact Barrett in binary64: n flip adds + 6 per modular product + 1 accumulate
+    return n + 6 * (n - 1) + 1
+
+
+def sync():
+    import torch
+    torch.cuda.synchronize()
+
+
+def roofline(ops_per_launch, walk_ms, launches, traffic=None):
+    avg_s = walk_ms / max(launches, 1) * 1e-3
+    achieved = ops_per_launch / avg_s / 1e12
+    peak = PEAK_LANE_OPS / 1e12
+    return {"bound": "alu", "achieved": round(achieved, 3), "peak": round(peak, 3),
+            "unit": "Tlane-op/s (FP64 VALU)", "frac": round(achieved / peak, 4),
+            "traffic": traffic, "kernel_avg_ms": round(avg_s * 1e3, 4),
+            "launches": launches}
+
+
+# ---------------------------------------------------------------- CPU baseline
+def cpu_baseline_schur(n, primes, seconds=12.0):
+    """Oracle Ryser mod p on S_n, bounded prefix, all host threads."""
+    from oracle import crt, native
+    mats = [crt.schur_residues(n, p) for p in primes]
+    threads = min(HOST_THREADS, os.cpu_count() or 1)
+    # calibrate one thread on a short prefix
+    t = time.perf_counter()
+    native.ryser_modp_prefix(mats[0], primes[0], 1 << 18)
+    rate1 = (1 << 18) / (time.perf_counter() - t)
+    per_thread = int(min(1 << n, max(1 << 18, rate1 * seconds)))
+    done = []
+
+    def work(i):
+        native.ryser_modp_prefix(mats[i % len(mats)], primes[i % len(primes)], per_thread)
+        done.append(per_thread - 1)
+
+    t = time.perf_counter()
+    ths = [threading.Thread(target=work, args=(i,)) for i in range(threads)]
+    for th in ths:
+        th.start()
+    for th in ths:
+        th.join()
+    dt = time.perf_counter() - t
+    ryser_subsets_per_s = sum(done) / dt
+    # one permanent = 2^n Ryser subsets on the CPU = 2^(n-1) Glynn terms in the metric
+    value = ryser_subsets_per_s / (1 << n) * (1 << (n - 1))
+    return {"value": value, "unit": "subset-terms/s (Glynn-term equivalents)", "cores": threads,
+            "kind": "oracle",
+            "sample": f"oracle Ryser mod p on S_{n}: first {per_thread - 1} of 2^{n} subsets per "
+                      f"thread, {threads} threads in {dt:.1f} s; rate scaled to 2^{n - 1} terms "
+                      f"per permanent"}
+
+
+def cpu_baseline_many(mats, field, seconds=10.0):
+    from oracle import native
+    threads = min(HOST_THREADS, os.cpu_count() or 1)
+    t = time.perf_counter()
+    native.ryser_many(mats[:2])
+    per = (time.perf_counter() - t) / 2
+    k = max(1, min(len(mats) // threads, int(seconds / max(per, 1e-9))))
+    done = []
+
+    def work(i):
+        native.ryser_many(mats[i * k:(i + 1) * k])
+        done.append(k)
+
+    t = time.perf_counter()
+    ths = [threading.Thread(target=work, args=(i,)) for i in range(threads)]
+    for th in ths:
+        th.start()
+    for th in ths:
+        th.join()
+    dt = time.perf_counter() - t
+    return {"value": sum(done) / dt, "unit": "perms/s", "cores": threads, "kind": "oracle",
+            "sample": f"oracle Ryser on {sum(done)} of the {field} matrices ({threads} threads, "
+                      f"{dt:.1f} s)"}
+
+
+# ------------------------------------------------------------------ workloads
+def bench_schur(P, ctx, args):
+    import torch
+    n = 28
+    primes = P.perm_schur_primes(n)
+    mats = torch.from_numpy(np.stack([P.perm_schur_residues(n, p) for p in primes])
+                            .astype(np.int32)).cuda()
+    bound = (n / 2) * math.log2(n)
+    for _ in range(args.warmup):
+        val, res = P.perm_crt_int(ctx, mats, primes, bound)
+    sync()
+    P.perm_prof_enable(ctx, True)
+    P.perm_prof_read(ctx)
+    t0 = time.perf_counter()
+    for _ in range(args.steps):
+        val, res = P.perm_crt_int(ctx, mats, primes, bound)
+    sync()
+    dt = time.perf_counter() - t0
+    walk_ms, launches = P.perm_prof_read(ctx)
+    P.perm_prof_enable(ctx, False)
+    assert val == 0 and res == [0] * len(primes), (val, res)   # even n: perm(S_n) = 0
+    terms = len(primes) * (1 << (n - 1))
+    line = {
+        "metric": METRIC, "value": terms * args.steps / dt, "unit": "subset-terms/s",
+        "ms_per_step": dt / args.steps * 1e3, "dtype": "f64",
+        "config": {"workload": "schur_S28_crt_3primes", "n": n, "primes": primes,
+                   "field": "F_p (exact FP64 Barrett walk) + CRT", "terms_per_step": terms,
+                   "perm": val},
+        "roofline": roofline(terms * ops_per_term("modp", n), walk_ms, launches),
+    }
+    if not args.no_cpu:
+        line["cpu_baseline"] = cpu_baseline_schur(n, primes)
+    return line
+
+
+def bench_single14(P, ctx, args):
+    import torch
+    from paper_2602_10141_amd import ensembles as E
+    U = torch.from_numpy(E.haar_unitary(14, E.rng(1, 0))).cuda()
+    for _ in range(args.warmup):
+        out = P.perm_c128(ctx, U)
+    sync()
+    P.perm_prof_enable(ctx, True)
+    P.perm_prof_read(ctx)
+    t0 = time.perf_counter()
+    for _ in range(args.steps):
+        out = P.perm_c128(ctx, U)
+    sync()
+    dt = time.perf_counter() - t0
+    walk_ms, launches = P.perm_prof_read(ctx)
+    P.perm_prof_enable(ctx, False)
+    terms = 1 << 13
+    return {"metric": METRIC, "value": args.steps / dt, "unit": "perms/s",
+            "ms_per_step": dt / args.steps * 1e3, "dtype": "f64",
+            "config": {"workload": "haar_unitary_14_c128", "n": 14},
+            "roofline": roofline(terms * ops_per_term("c128", 14), walk_ms, launches)}
+
+
+def bench_haar20(P, ctx, args):
+    import torch
+    from paper_2602_10141_amd import ensembles as E
+    n, count = 20, args.count
+    U = E.haar_unitary(n, E.rng(3, 0), count=count)
+    O = E.haar_orthogonal(n, E.rng(3, 1), count=count)
+    out = {}
+    for name, M, field in (("c128", U, "c128"), ("f64", O, "f64")):
+        items, data = P.pack_matrices([(m, field, 0) for m in M])
+        d = torch.from_numpy(data).cuda()
+        res = torch.zeros((count, 2), dtype=torch.float64, device="cuda")
+        for _ in range(max(1, args.warmup)):
+            P.perm_batch(ctx, items, d, out=res)
+        sync()
+        P.perm_prof_enable(ctx, True)
+        P.perm_prof_read(ctx)
+        t0 = time.perf_counter()
+        steps = max(1, args.steps // 20)
+        for _ in range(steps):
+            P.perm_batch(ctx, items, d, out=res)
+        sync()
+        dt = (time.perf_counter() - t0) / steps
+        walk_ms, launches = P.perm_prof_read(ctx)
+        P.perm_prof_enable(ctx, False)
+        terms = count * (1 << (n - 1))
+        out[name] = {"perms_per_s": count / dt, "terms_per_s": terms / dt, "ms": dt * 1e3,
+                     "roofline": roofline(terms * ops_per_term(field, n), walk_ms, launches)}
+    line = {"metric": METRIC, "value": out["c128"]["terms_per_s"], "unit": "subset-terms/s",
+            "ms_per_step": out["c128"]["ms"] + out["f64"]["ms"], "dtype": "f64",
+            "config": {"workload": "haar20_batched", "count": count, "n": n},
+            "roofline": out["c128"]["roofline"], "detail": out}
+    if not args.no_cpu:
+        line["cpu_baseline"] = cpu_baseline_many(U[:4000], "Haar U(20) c128")
+    return line
+
+
+def ragged_inputs(count, seed=4):
+    from paper_2602_10141_amd import ensembles as E
+    g = E.rng(seed, 0)
+    ns = g.integers(8, 25, size=count)
+    kinds = g.integers(0, 4, size=count)
+    mats = []
+    for n, k in zip(ns, kinds):
+        n = int(n)
+        if k == 0:
+            mats.append((E.gue(n, g), "c128", 0))
+        elif k == 1:
+            mats.append((E.goe(n, g), "f64", 0))
+        elif k == 2:
+            mats.append((E.ginibre_real(n, g), "f64", 0))
+        else:
+            mats.append((E.ginibre_complex(n, g), "c128", 0))
+    return mats
+
+
+def bench_ragged(P, ctx, args):
+    import torch
+    mats = ragged_inputs(args.count)
+    items, data = P.pack_matrices(mats)
+    d = torch.from_numpy(data).cuda()
+    res = torch.zeros((len(mats), 2), dtype=torch.float64, device="cuda")
+    for _ in range(max(1, args.warmup)):
+        P.perm_batch(ctx, items, d, out=res)
+    sync()
+    P.perm_prof_enable(ctx, True)
+    P.perm_prof_read(ctx)
+    steps = max(1, args.steps // 20)
+    t0 = time.perf_counter()
+    for _ in range(steps):
+        P.perm_batch(ctx, items, d, out=res)
+    sync()
+    dt = (time.perf_counter() - t0) / steps
+    walk_ms, launches = P.perm_prof_read(ctx)
+    P.perm_prof_enable(ctx, False)
+    terms = sum(1 << (m[0].shape[0] - 1) for m in mats)
+    ops = sum((1 << (m[0].shape[0] - 1)) * ops_per_term(m[1], m[0].shape[0]) for m in mats)
+    return {"metric": METRIC, "value": len(mats) / dt, "unit": "perms/s", "ms_per_step": dt * 1e3,
+            "dtype": "f64", "config": {"workload": "ragged_gaussian_n8_24", "count": len(mats),
+                                       "terms": terms},
+            "roofline": roofline(ops, walk_ms, launches)}
+
+
+WORKLOADS = {"schur28": bench_schur, "single14": bench_single14, "haar20": bench_haar20,
+             "ragged": bench_ragged}
+
+
+def main():
+    ap = argparse.ArgumentParser()
+    ap.add_argument("--gpus", type=int, default=1)
+    ap.add_argument("--steps", type=int, default=100)
+    ap.add_argument("--warmup", type=int, default=10)
+    ap.add_argument("--workload", default="schur28", choices=sorted(WORKLOADS))
+    ap.add_argument("--count", type=int, default=50000)
+    ap.add_argument("--no-cpu", action="store_true", help="skip the oracle CPU baseline")
+    args = ap.parse_args()
+    if args.gpus != 1:
+        print(f"bench.py runs on one GPU only (asked for {args.gpus}); the path shards by "
+              "Gray-index range or by prime, see DESIGN.md", file=sys.stderr)
+        sys.exit(2)
+    if args.workload == "ragged" and args.count == 50000:
+        args.count = 10000
+    import torch
+    if not torch.cuda.is_available():
+        print("no GPU visible", file=sys.stderr)
+        sys.exit(1)
+    from paper_2602_10141_amd import perm as P
+    ctx = P.Context(0)
+    try:
+        line = WORKLOADS[args.workload](P, ctx, args)
+    finally:
+        ctx.close()
+    base = {"metric": METRIC, "n_gpus": 1, "steps": args.steps, "warmup": args.warmup,
+            "higher_is_better": True, "scaling": "weak", "vs_baseline": None,
+            "data": "synthetic"}
+    base.update(line)
+    order = ["metric", "value", "unit", "n_gpus", "steps", "warmup", "ms_per_step",
+             "higher_is_better", "scaling", "vs_baseline", "dtype", "data", "config",
+             "roofline", "cpu_baseline"]
+    out = {k: base[k] for k in order if k in base}
+    out.update({k: v for k, v in base.items() if k not in out})
+    print(json.dumps(out), flush=True)
+
+
+if __name__ == "__main__":
+    main()

@@ -142,6 +142,13 @@ int perm_batch(perm_ctx *ctx, const perm_item *items, int count, const void *dat
 int perm_range(perm_ctx *ctx, const perm_item *item, const void *data, uint64_t x0, uint64_t x1,
                void *out16, unsigned flags, void *stream);
 
+/* Walk-kernel timing.  While enabled, the context records a pair of HIP
+ * events around every walk-kernel launch, on the stream the kernel runs on.
+ * perm_prof_read waits for the recorded launches, returns their summed
+ * device time in milliseconds and their count, and clears the record. */
+int perm_prof_enable(perm_ctx *ctx, int on);
+int perm_prof_read(perm_ctx *ctx, double *walk_ms, uint64_t *launches);
+
 /* ---------------------------------------------------------------- helpers
  * Host-only; no device needed. */
 

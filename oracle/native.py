@@ -28,6 +28,7 @@ def lib():
             ("oracle_ryser_c128_ld", [dp, c_int, dp]),
             ("oracle_ryser_f64", [dp, c_int, c_int, dp]),
             ("oracle_ryser_modp", [u32p, c_int, c_u32, u32p]),
+            ("oracle_ryser_modp_prefix", [u32p, c_int, c_u32, u64, u32p]),
             ("oracle_glynn_range_c128", [dp, c_int, u64, u64, dp]),
             ("oracle_glynn_range_f64", [dp, c_int, u64, u64, dp]),
             ("oracle_glynn_range_modp", [u32p, c_int, c_u32, u64, u64, u32p]),
@@ -82,6 +83,14 @@ def ryser_modp(A, p: int) -> int:
     A, n = _mat(A, np.uint32)
     out = np.zeros(1, dtype=np.uint32)
     _check(lib().oracle_ryser_modp(A.ctypes.data, n, int(p), out.ctypes.data))
+    return int(out[0])
+
+
+def ryser_modp_prefix(A, p: int, x_end: int) -> int:
+    """Signed Ryser sum mod p over the first x_end - 1 Gray-ordered subsets."""
+    A, n = _mat(A, np.uint32)
+    out = np.zeros(1, dtype=np.uint32)
+    _check(lib().oracle_ryser_modp_prefix(A.ctypes.data, n, int(p), x_end, out.ctypes.data))
     return int(out[0])
 
 

@@ -149,17 +149,15 @@ int oracle_ryser_f64(const double *A, int n, int kahan, double *out)
 }
 
 /* ----------------------------------------------------------------- F_p */
-int oracle_ryser_modp(const uint32_t *A, int n, uint32_t p, uint32_t *out)
+/* Signed Ryser sum over the Gray-ordered subsets x = 1 .. x_end-1, mod p
+ * (without the final (-1)^n).  x_end = 2^n gives the whole sum. */
+static int ryser_modp_upto(const uint32_t *A, int n, uint32_t p, uint64_t x_end, uint64_t *tot_out)
 {
-    if (n < 0 || n > ORACLE_NMAX || !out || p < 2 || (n > 0 && !A)) return -1;
-    for (int i = 0; i < n * n; ++i) if (A[i] >= p) return -1;
-    if (n == 0) { out[0] = 1u % p; return 0; }
     const uint64_t P = p;
     uint64_t s[ORACLE_NMAX];
     for (int i = 0; i < n; ++i) s[i] = 0;
     uint64_t tot = 0;
-    const uint64_t nsub = (uint64_t)1 << n;
-    for (uint64_t x = 1; x < nsub; ++x) {
+    for (uint64_t x = 1; x < x_end; ++x) {
         unsigned j = ctz64(x);
         uint64_t g = x ^ (x >> 1);
         int enters = (int)((g >> j) & 1u);
@@ -173,7 +171,31 @@ int oracle_ryser_modp(const uint32_t *A, int n, uint32_t p, uint32_t *out)
         if (x & 1u) tot = (tot + P - prod) % P;
         else        tot = (tot + prod) % P;
     }
-    if (n & 1) tot = (P - tot) % P;
+    *tot_out = tot;
+    return 0;
+}
+
+int oracle_ryser_modp(const uint32_t *A, int n, uint32_t p, uint32_t *out)
+{
+    if (n < 0 || n > ORACLE_NMAX || !out || p < 2 || (n > 0 && !A)) return -1;
+    for (int i = 0; i < n * n; ++i) if (A[i] >= p) return -1;
+    if (n == 0) { out[0] = 1u % p; return 0; }
+    uint64_t tot = 0;
+    ryser_modp_upto(A, n, p, (uint64_t)1 << n, &tot);
+    if (n & 1) tot = (p - tot) % p;
+    out[0] = (uint32_t)tot;
+    return 0;
+}
+
+/* The first x_end - 1 subsets of the walk above: the same per-subset work on
+ * a bounded prefix, used to time the oracle on matrices too large to finish. */
+int oracle_ryser_modp_prefix(const uint32_t *A, int n, uint32_t p, uint64_t x_end, uint32_t *out)
+{
+    if (n < 1 || n > ORACLE_NMAX || !out || p < 2 || !A) return -1;
+    if (n < 64 && x_end > ((uint64_t)1 << n)) return -1;
+    for (int i = 0; i < n * n; ++i) if (A[i] >= p) return -1;
+    uint64_t tot = 0;
+    ryser_modp_upto(A, n, p, x_end, &tot);
     out[0] = (uint32_t)tot;
     return 0;
 }

@@ -71,6 +71,8 @@ struct perm_ctx {
     int grid_per_cu = 0;
     std::map<std::pair<int, int>, perm_tune> tune;
     std::map<int, int> occ;
+    bool prof_on = false;
+    std::vector<std::pair<hipEvent_t, hipEvent_t>> prof_pending, prof_pool;
 };
 
 namespace permi {

@@ -369,12 +369,27 @@ int execute(perm_ctx *ctx, Plan &pl, const void *src, void *out, size_t out_slot
         const int blocks_needed = (int)((g.count + (BLOCK / WAVE) - 1) / (BLOCK / WAVE));
         const int grid = std::max(1, std::min(blocks_needed, per_cu * ctx->num_cus));
         uint64_t adv = 0;
+        std::pair<hipEvent_t, hipEvent_t> ev{nullptr, nullptr};
+        if (ctx->prof_on) {
+            if (ctx->prof_pool.empty()) {
+                HIPCHK(hipEventCreate(&ev.first));
+                HIPCHK(hipEventCreate(&ev.second));
+            } else {
+                ev = ctx->prof_pool.back();
+                ctx->prof_pool.pop_back();
+            }
+            HIPCHK(hipEventRecord(ev.first, s));
+        }
         HIPCHK((hipError_t)launch_walk(g.variant, g.n, g.kahan, g.fused, g.nmax_fused,
                                        d_items + g.first_item, g.count, d_mats, ctx->stage.p,
                                        (double *)ctx->partials.p,
                                        (unsigned long long *)ctx->ctr.p, ctx->ctr_value, grid, s,
                                        &adv));
         ctx->ctr_value += adv;
+        if (ctx->prof_on) {
+            HIPCHK(hipEventRecord(ev.second, s));
+            ctx->prof_pending.push_back(ev);
+        }
     }
     HIPCHK((hipError_t)launch_finalize(d_mats, (int)pl.mats.size(), (const double *)ctx->partials.p,
                                        out, s));
@@ -431,6 +446,11 @@ extern "C" void perm_ctx_destroy(perm_ctx *c)
     for (DevBuf *b : {&c->src, &c->stage, &c->partials, &c->outs, &c->plan_buf, &c->ctr})
         if (b->p) (void)hipFree(b->p);
     if (c->pinned) (void)hipHostFree(c->pinned);
+    for (auto *v : {&c->prof_pending, &c->prof_pool})
+        for (auto &e : *v) {
+            (void)hipEventDestroy(e.first);
+            (void)hipEventDestroy(e.second);
+        }
     if (c->last_ev) (void)hipEventDestroy(c->last_ev);
     if (c->pinned_ev) (void)hipEventDestroy(c->pinned_ev);
     if (c->stream) (void)hipStreamDestroy(c->stream);
@@ -712,6 +732,32 @@ extern "C" int perm_crt_int(perm_ctx *ctx, const uint32_t *mats, const uint32_t 
     if (!permh::garner_lift(res.data(), primes, k, mag, sg)) return fail(PERM_EINVAL, "lift failed");
     if ((rc = write_limbs(mag, sg, limbs, max_limbs, nlimbs, sign)) != PERM_OK) return rc;
     if (residues_out) std::memcpy(residues_out, res.data(), (size_t)k * 4);
+    return PERM_OK;
+}
+
+// --------------------------------------------------------------- profiling
+extern "C" int perm_prof_enable(perm_ctx *ctx, int on)
+{
+    if (!ctx) return fail(PERM_EINVAL, "ctx is NULL");
+    ctx->prof_on = on != 0;
+    return PERM_OK;
+}
+
+extern "C" int perm_prof_read(perm_ctx *ctx, double *walk_ms, uint64_t *launches)
+{
+    if (!ctx || !walk_ms || !launches) return fail(PERM_EINVAL, "NULL argument");
+    HIPCHK(hipSetDevice(ctx->device));
+    double tot = 0.0;
+    for (auto &e : ctx->prof_pending) {
+        HIPCHK(hipEventSynchronize(e.second));
+        float ms = 0.0f;
+        HIPCHK(hipEventElapsedTime(&ms, e.first, e.second));
+        tot += ms;
+    }
+    *walk_ms = tot;
+    *launches = ctx->prof_pending.size();
+    ctx->prof_pool.insert(ctx->prof_pool.end(), ctx->prof_pending.begin(), ctx->prof_pending.end());
+    ctx->prof_pending.clear();
     return PERM_OK;
 }
 

@@ -68,6 +68,8 @@ _SIGS = {
     "perm_crt_int": ([_P, _P, _P, _I, _I, _D, _P, _I, _P, _P, _P, _U, _P], _I),
     "perm_batch": ([_P, _P, _I, _P, _P, _P, _U, _P], _I),
     "perm_range": ([_P, _P, _P, _U64, _U64, _P, _U, _P], _I),
+    "perm_prof_enable": ([_P, _I], _I),
+    "perm_prof_read": ([_P, _P, _P], _I),
     "perm_schur_primes": ([_I, _I, _P, _I, _P], _I),
     "perm_schur_residues": ([_I, ctypes.c_uint32, _P], _I),
     "perm_crt_lift": ([_P, _P, _I, _D, _P, _I, _P, _P], _I),
@@ -342,6 +344,18 @@ def perm_range(ctx, item, data, x0: int, x1: int, flags=0):
     _check(lib().perm_range(ctx.ptr, it.ctypes.data, d.ctypes.data, x0, x1, out.ctypes.data,
                             flags & ~PERM_DEVICE_PTRS, None))
     return batch_values(it, out.reshape(1, 2))[0]
+
+
+# --------------------------------------------------------------- profiling
+def perm_prof_enable(ctx, on=True):
+    _check(lib().perm_prof_enable(ctx.ptr, int(bool(on))))
+
+
+def perm_prof_read(ctx):
+    """(summed walk-kernel milliseconds, launches) since the last read."""
+    ms, n = ctypes.c_double(), ctypes.c_uint64()
+    _check(lib().perm_prof_read(ctx.ptr, ctypes.byref(ms), ctypes.byref(n)))
+    return ms.value, n.value
 
 
 # ------------------------------------------------------------------ tuning
