@@ -259,7 +259,93 @@ def bench_ragged(P, ctx, args):
             "roofline": roofline(ops, walk_ms, launches)}
 
 
-WORKLOADS = {"schur28": bench_schur, "single14": bench_single14, "haar20": bench_haar20,
+def serve_requests(P):
+    """512 geodesic points (odd n in 11..25, 64-point t grid, principal branch,
+    c128) and 18 Schur residue matrices (n in 32, 34, 36; six primes each)."""
+    from paper_2602_10141_amd import ensembles as E
+    reqs = []
+    for n in range(11, 26, 2):
+        for t in E.geodesic_grid(64):
+            reqs.append((E.cycle_geodesic(n, t), "c128", 0, "geodesic", n))
+    for n in (32, 34, 36):
+        k = len(P.perm_schur_primes(n))
+        for p in P.perm_schur_primes(n, extra=6 - k):
+            reqs.append((P.perm_schur_residues(n, p), "modp", p, "schur", n))
+    order = E.rng(5, 0).permutation(len(reqs))
+    return [reqs[i] for i in order]
+
+
+def _serve_run(P, ctx, reqs, rate, seed, slice_us):
+    """Submit reqs with exponential inter-arrival times of mean 1/rate (rate =
+    None: all at once); collect results and per-request latencies."""
+    import threading as th
+    srv = P.Server(ctx, hbm_budget=8 << 30, slice_us=slice_us)
+    g = np.random.Generator(np.random.PCG64(np.random.SeedSequence([260210141, 5, seed])))
+    gaps = g.exponential(1.0 / rate, size=len(reqs)) if rate else np.zeros(len(reqs))
+    tickets = [None] * len(reqs)
+    t0 = time.perf_counter()
+
+    def submitter():
+        t = t0
+        for i, (A, f, p, _, _) in enumerate(reqs):
+            t += gaps[i]
+            d = t - time.perf_counter()
+            if d > 0:
+                time.sleep(d)
+            tickets[i] = srv.submit(A, f, p)
+
+    sub = th.Thread(target=submitter)
+    sub.start()
+    vals, lats = [None] * len(reqs), [0.0] * len(reqs)
+    for i in range(len(reqs)):
+        while tickets[i] is None:
+            time.sleep(0.0002)
+        vals[i], lats[i] = srv.wait(tickets[i][0], tickets[i][1], timeout_s=600, with_latency=True)
+    sub.join()
+    wall = time.perf_counter() - t0
+    st = srv.stats()
+    srv.close()
+    return vals, np.array(lats), wall, st
+
+
+def _pcts(x):
+    return {"p50_us": float(np.percentile(x, 50)), "p99_us": float(np.percentile(x, 99)),
+            "mean_us": float(np.mean(x)), "count": int(len(x))}
+
+
+def bench_serve(P, ctx, args):
+    reqs = serve_requests(P)
+    terms = sum(1 << (r[0].shape[0] - 1) for r in reqs)
+    slice_us = 2000.0
+    _serve_run(P, ctx, reqs[:40], None, 0, slice_us)                 # warm-up
+    vals, lats, wall, st = _serve_run(P, ctx, reqs, None, 1, slice_us)
+    sat_rate = len(reqs) / wall
+    cls = np.array([r[3] for r in reqs])
+    result = {"saturation": {"wall_s": wall, "requests_per_s": sat_rate,
+                             "terms_per_s": terms / wall, **_pcts(lats),
+                             "geodesic": _pcts(lats[cls == "geodesic"]),
+                             "schur": _pcts(lats[cls == "schur"])}}
+    ref = vals
+    for f in (0.5, 0.7, 0.9):
+        v, l, w, s2 = _serve_run(P, ctx, reqs, f * sat_rate, 2 + int(f * 10), slice_us)
+        assert v == ref, "served results differ between runs"
+        result[f"load_{f}"] = {"wall_s": w, "offered_per_s": f * sat_rate, **_pcts(l),
+                               "geodesic": _pcts(l[cls == "geodesic"]),
+                               "schur": _pcts(l[cls == "schur"])}
+    # every Schur residue is 0 for even n; geodesic perms are real and |.| <= 1
+    for r, v in zip(reqs, ref):
+        if r[3] == "schur":
+            assert v == 0
+        else:
+            assert abs(v.imag) < 1e-12 and abs(v) <= 1 + 1e-12
+    return {"metric": METRIC, "value": terms / wall, "unit": "subset-terms/s",
+            "ms_per_step": wall * 1e3, "dtype": "f64",
+            "config": {"workload": "serve_geodesic_c128_and_schur_modp", "requests": len(reqs),
+                       "terms": terms, "slice_us": slice_us},
+            "latency": result}
+
+
+WORKLOADS = {"serve": bench_serve, "schur28": bench_schur, "single14": bench_single14, "haar20": bench_haar20,
              "ragged": bench_ragged}
 
 

@@ -226,11 +226,13 @@ int perm_srv_submit(perm_srv *srv, const perm_item *item, const void *matrix, ui
 /* *done = 1 and out16 filled (perm_batch slot format) once finished; returns
  * the request's status (PERM_OK, PERM_ECANCELED, PERM_EDEVICE) when done,
  * PERM_OK with *done = 0 while running, PERM_ENOTFOUND for an unknown or
- * already collected ticket.  A finished ticket is forgotten after it is
- * reported done. */
-int perm_srv_poll(perm_srv *srv, uint64_t ticket, void *out16, int *done);
+ * already collected ticket.  latency_us (optional) receives the time from
+ * submit to the result becoming visible on the host.  A finished ticket is
+ * forgotten after it is reported done. */
+int perm_srv_poll(perm_srv *srv, uint64_t ticket, void *out16, int *done, double *latency_us);
 /* Block until the ticket finishes or timeout_s passes (then *done = 0). */
-int perm_srv_wait(perm_srv *srv, uint64_t ticket, double timeout_s, void *out16, int *done);
+int perm_srv_wait(perm_srv *srv, uint64_t ticket, double timeout_s, void *out16, int *done,
+                  double *latency_us);
 int perm_srv_cancel(perm_srv *srv, uint64_t ticket);
 int perm_srv_get_stats(perm_srv *srv, perm_srv_stats *out);
 /* Stop accepting, finish or cancel everything, join the worker. */

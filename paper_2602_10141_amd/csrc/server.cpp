@@ -667,7 +667,8 @@ extern "C" int perm_srv_submit(perm_srv *S, const perm_item *item, const void *m
     return PERM_OK;
 }
 
-extern "C" int perm_srv_poll(perm_srv *S, uint64_t ticket, void *out16, int *done)
+extern "C" int perm_srv_poll(perm_srv *S, uint64_t ticket, void *out16, int *done,
+                             double *latency_us)
 {
     if (!S || !done) return fail(PERM_EINVAL, "NULL argument");
     std::lock_guard<std::mutex> lk(S->mu);
@@ -681,11 +682,13 @@ extern "C" int perm_srv_poll(perm_srv *S, uint64_t ticket, void *out16, int *don
     *done = 1;
     const int st = r.status;
     if (out16 && st == PERM_OK) std::memcpy(out16, r.result, 16);
+    if (latency_us) *latency_us = r.t_done - r.t_submit;
     if (!referenced) S->reqs.erase(it);
     return st;
 }
 
-extern "C" int perm_srv_wait(perm_srv *S, uint64_t ticket, double timeout_s, void *out16, int *done)
+extern "C" int perm_srv_wait(perm_srv *S, uint64_t ticket, double timeout_s, void *out16, int *done,
+                             double *latency_us)
 {
     if (!S || !done) return fail(PERM_EINVAL, "NULL argument");
     {
@@ -697,7 +700,7 @@ extern "C" int perm_srv_wait(perm_srv *S, uint64_t ticket, double timeout_s, voi
             return it == S->reqs.end() || it->second.state == R_DONE;
         });
     }
-    return perm_srv_poll(S, ticket, out16, done);
+    return perm_srv_poll(S, ticket, out16, done, latency_us);
 }
 
 extern "C" int perm_srv_cancel(perm_srv *S, uint64_t ticket)

@@ -445,16 +445,25 @@ template <int N, bool K> struct OpsFor<V_MONT, N, K> { using type = OpsMont<N>; 
 // 4m+3 flip column 1 (down, then up); step 4m+2 flips column 2, down for even
 // m and up for odd m; step 4m flips column b+1 with b = ctz(4m), up exactly
 // when bit b+1 of j is set.
+// Keep each step's instructions (and its column loads) between step
+// boundaries: letting the scheduler pull future steps' scalar loads forward
+// overflows the SGPR file; the load latency is hidden by the other waves.
+__device__ __forceinline__ void step_boundary() { __builtin_amdgcn_sched_barrier(0); }
+
 template <class Ops>
 __device__ __forceinline__ void group_tail(Ops &S, uint32_t m)
 {
     S.template term<false>();
+    step_boundary();
     S.flip(S.col(1, true));
     S.template term<true>();
+    step_boundary();
     S.flip(S.col(2, !(m & 1)));
     S.template term<false>();
+    step_boundary();
     S.flip(S.col(1, false));
     S.template term<true>();
+    step_boundary();
 }
 
 template <class Ops>
@@ -534,10 +543,27 @@ __device__ __forceinline__ uint32_t next_item(unsigned long long *ctr, uint64_t 
     return lo;
 }
 
+// Register budget per variant and order: the row sums plus the product
+// chains, Kahan state and addressing.  The kernel asks the compiler for the
+// matching number of waves per SIMD so that it does not buy extra overlap of
+// consecutive steps with registers that would cost occupancy.
+template <int V, int N>
+struct Occupancy {
+    static constexpr int regs = V == V_C128 ? 4 * N + 40
+                              : V == V_MONT ? N + 32
+                              : V == V_MODP ? 2 * N + 44
+                                            : 2 * N + 32;
+    static constexpr int w = 512 / regs;
+    static constexpr int waves = w < 1 ? 1 : (w > 8 ? 8 : w);
+};
+
 // Persistent kernel: every wave pulls wave items (largest first, as ordered
-// by the host) until the counter passes `count`.
-template <int V, int N, bool KAHAN>
-__global__ __launch_bounds__(BLOCK) void walk_kernel(const WaveItem *items, uint32_t count,
+// by the host) until the counter passes `count`.  W > 0 overrides the
+// waves-per-SIMD target (used when tuning the budgets).
+template <int V, int N, bool KAHAN, int W = 0>
+__global__ __launch_bounds__(BLOCK)
+__attribute__((amdgpu_waves_per_eu(W > 0 ? W : Occupancy<V, N>::waves, 8)))
+void walk_kernel(const WaveItem *items, uint32_t count,
                                                      const MatDesc *mats, const char *stage,
                                                      double *partials, unsigned long long *ctr,
                                                      uint64_t base)

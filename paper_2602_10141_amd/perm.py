@@ -80,8 +80,8 @@ _SIGS = {
     "perm_tune_load": ([_P, ctypes.c_char_p], _I),
     "perm_srv_create": ([_P, _P, _P], _I),
     "perm_srv_submit": ([_P, _P, _P, _P], _I),
-    "perm_srv_poll": ([_P, _U64, _P, _P], _I),
-    "perm_srv_wait": ([_P, _U64, _D, _P, _P], _I),
+    "perm_srv_poll": ([_P, _U64, _P, _P, _P], _I),
+    "perm_srv_wait": ([_P, _U64, _D, _P, _P, _P], _I),
     "perm_srv_cancel": ([_P, _U64], _I),
     "perm_srv_get_stats": ([_P, _P], _I),
     "perm_srv_destroy": ([_P], None),
@@ -407,20 +407,24 @@ class Server:
     def poll(self, ticket, it):
         buf = ctypes.create_string_buffer(16)
         done = ctypes.c_int()
-        rc = lib().perm_srv_poll(self.ptr, ticket, buf, ctypes.byref(done))
+        rc = lib().perm_srv_poll(self.ptr, ticket, buf, ctypes.byref(done), None)
         if rc != PERM_OK:
             raise PermError(rc, perm_last_error() if rc != PERM_ECANCELED else "cancelled")
         return (True, self._decode(it, buf.raw)) if done.value else (False, None)
 
-    def wait(self, ticket, it, timeout_s=60.0):
+    def wait(self, ticket, it, timeout_s=60.0, with_latency=False):
+        """Result of a ticket (and its submit-to-result latency in us if asked)."""
         buf = ctypes.create_string_buffer(16)
         done = ctypes.c_int()
-        rc = lib().perm_srv_wait(self.ptr, ticket, float(timeout_s), buf, ctypes.byref(done))
+        lat = ctypes.c_double()
+        rc = lib().perm_srv_wait(self.ptr, ticket, float(timeout_s), buf, ctypes.byref(done),
+                                 ctypes.byref(lat))
         if rc != PERM_OK:
             raise PermError(rc, perm_last_error() if rc != PERM_ECANCELED else "cancelled")
         if not done.value:
             raise TimeoutError(f"ticket {ticket} not done after {timeout_s} s")
-        return self._decode(it, buf.raw)
+        v = self._decode(it, buf.raw)
+        return (v, lat.value) if with_latency else v
 
     def cancel(self, ticket):
         _check(lib().perm_srv_cancel(self.ptr, ticket))
