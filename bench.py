@@ -345,7 +345,27 @@ def bench_serve(P, ctx, args):
             "latency": result}
 
 
-WORKLOADS = {"serve": bench_serve, "schur28": bench_schur, "single14": bench_single14, "haar20": bench_haar20,
+def bench_copycal(P, ctx, args):
+    """A plain device copy of known size: the reference for scaling the
+    FETCH_SIZE / WRITE_SIZE counters of a profiled run."""
+    import torch
+    nbytes = 1 << 30
+    x = torch.ones(nbytes // 8, dtype=torch.float64, device="cuda")
+    y = torch.empty_like(x)
+    sync()
+    t0 = time.perf_counter()
+    reps = max(1, args.steps // 20)
+    for _ in range(reps):
+        y.copy_(x)
+    sync()
+    dt = (time.perf_counter() - t0) / reps
+    return {"metric": "copy bandwidth", "value": 2 * nbytes / dt / 1e9, "unit": "GB/s",
+            "ms_per_step": dt * 1e3, "dtype": "f64",
+            "config": {"workload": "copy_calibration", "bytes_read": nbytes,
+                       "bytes_written": nbytes, "copies": reps}}
+
+
+WORKLOADS = {"copycal": bench_copycal, "serve": bench_serve, "schur28": bench_schur, "single14": bench_single14, "haar20": bench_haar20,
              "ragged": bench_ragged}
 
 

@@ -123,11 +123,14 @@ static int ensure_pinned(perm_ctx *ctx, size_t bytes)
 // ------------------------------------------------------------------ tuning
 int default_log2_chunk(int variant, int n)
 {
-    // 64 * 2^c indices per wave item; c in [10, 20] keeps the per-lane seed
-    // (n^2 work) under 1% of the walk and at most 2^20 items per matrix.
+    // 64 * 2^c indices per wave item.  Up to n = 20 about eight items per
+    // matrix (short walks keep a single small permanent's latency low; these
+    // orders are a small share of any batch's work).  Beyond, c in [10, 20]
+    // keeps the per-lane seed (n^2 work) under 1% of the walk and a matrix
+    // at most 2^20 items.
     (void)variant;
-    int c = std::min(std::max(n - 27, 10), 20);
-    return c;
+    if (n <= 20) return std::max(3, n - 10);
+    return std::min(std::max(n - 27, 10), 20);
 }
 
 int log2_chunk_for(const perm_ctx *ctx, int variant, int n)
@@ -263,11 +266,21 @@ int plan(perm_ctx *ctx, const std::vector<MatIn> &in, Plan &pl)
             d.num_parts = np;
             pl.nparts += np;
         }
-        std::stable_sort(gi.begin(), gi.end(), [&](const WaveItem &u, const WaveItem &v) {
-            const double cu = (double)u.nlanes * std::ldexp(1.0, (int)u.log2L) * in[u.mat].n;
-            const double cv = (double)v.nlanes * std::ldexp(1.0, (int)v.log2L) * in[v.mat].n;
-            return cu > cv;
-        });
+        // largest first (stable): key = indices per item x n
+        std::vector<std::pair<uint64_t, uint32_t>> key(gi.size());
+        bool uniform = true;
+        for (size_t q = 0; q < gi.size(); ++q) {
+            key[q] = {((uint64_t)gi[q].nlanes << gi[q].log2L) * (uint64_t)in[gi[q].mat].n, (uint32_t)q};
+            uniform = uniform && key[q].first == key[0].first;
+        }
+        if (!uniform) {
+            std::stable_sort(key.begin(), key.end(),
+                             [](const std::pair<uint64_t, uint32_t> &a,
+                                const std::pair<uint64_t, uint32_t> &b) { return a.first > b.first; });
+            std::vector<WaveItem> sorted(gi.size());
+            for (size_t q = 0; q < gi.size(); ++q) sorted[q] = gi[key[q].second];
+            gi.swap(sorted);
+        }
         pl.items.insert(pl.items.end(), gi.begin(), gi.end());
         gd.count = (uint32_t)gi.size();
         pl.groups.push_back(gd);

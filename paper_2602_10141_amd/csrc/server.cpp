@@ -8,8 +8,12 @@
 // slices: each slice takes items from all admitted requests, shortest
 // remaining work first with a guaranteed share for the oldest request, up to
 // a work budget calibrated to `slice_us` of device time, launches the walk,
-// and finalizes the requests whose last items it carried.  Up to two slices
-// are in flight, so requests submitted while a slice runs join the next one.
+// and finalizes the requests whose last items it carried.  Slices alternate
+// between two streams, so the next slice's waves start on compute units as
+// soon as the current slice's waves drain, and requests submitted while a
+// slice runs join the next one.  Ordering across the two streams: a slice
+// waits (on the device) for the staging of requests admitted by the previous
+// slice, and a finalize waits for the previous slice to complete.
 #include <hip/hip_runtime.h>
 
 #include <algorithm>
@@ -93,7 +97,12 @@ struct Req {
     size_t off = 0, bytes = 0;
     int slot = -1;                       // row of the device MatDesc table
     MatDesc md{};
-    std::vector<WaveItem> items;         // in slot order
+    // wave items, generated on demand in slot order: item i covers
+    // [i * nlanes * 2^log2L, (i+1) * nlanes * 2^log2L) -- the split perm_batch
+    // makes of a full index range
+    int chunk = 0;                       // log2 chunk length fixed at submit
+    uint32_t log2L = 0, nlanes = 0;
+    size_t nitems = 0;
     size_t next = 0;                     // first item not yet scheduled
     int inflight_slices = 0;
     double work = 0;                     // remaining lane-steps x n (scheduling key)
@@ -101,8 +110,9 @@ struct Req {
 };
 
 struct Slice {
-    hipEvent_t done = nullptr;
-    hipEvent_t start = nullptr;
+    hipEvent_t done = nullptr;           // end of all of the slice's work
+    hipEvent_t staged = nullptr;         // after its staging kernel (if any)
+    bool has_staged = false;
     void *pinned = nullptr;
     size_t pinned_cap = 0;
     std::vector<uint64_t> finishing;     // tickets finalized by this slice
@@ -112,6 +122,17 @@ struct Slice {
 };
 
 constexpr size_t kSliceItems = 1 << 17;   // wave items per slice, at most
+
+WaveItem request_item(const Req &r, size_t i)
+{
+    WaveItem it{};
+    it.x0 = (uint64_t)i * ((uint64_t)r.nlanes << r.log2L);
+    it.mat = (uint32_t)r.slot;
+    it.slot = r.md.first_part + (uint32_t)i;
+    it.log2L = r.log2L;
+    it.nlanes = r.nlanes;
+    return it;
+}
 
 double item_work(const WaveItem &it, int n)
 {
@@ -123,13 +144,14 @@ double item_work(const WaveItem &it, int n)
 struct perm_srv {
     perm_ctx *ctx = nullptr;
     perm_srv_cfg cfg{};
-    hipStream_t stream = nullptr;
     void *arena_dev = nullptr;
     Arena arena;
     void *table_dev = nullptr;           // max_inflight MatDescs
     void *results_dev = nullptr;         // max_inflight * 16 bytes
-    void *ctr_dev = nullptr;
-    uint64_t ctr_value = 0;
+    void *ctr_dev = nullptr;             // one 64-bit counter per stream (256 B apart)
+    uint64_t ctr_value[2] = {0, 0};
+    hipStream_t streams[2] = {nullptr, nullptr};
+    bool prev_done_valid = false;        // slices[cur ^ 1].done refers to the previous slice
     std::vector<int> free_slots;
     Slice slices[2];
     int cur = 0;
@@ -219,40 +241,38 @@ void layout(perm_srv *S, Req &r)
     d.pinv = r.p ? 1.0 / (double)r.p : 0.0;
     d.mont_pp = r.variant == V_MONT ? permh::mont_pprime(r.p) : 0;
     d.out_slot = 0;
-    // items: the same split perm_batch uses for a full matrix
-    r.items.clear();
+    // items: the same split perm_batch makes of the full range [0, 2^(n-1))
+    r.nitems = 0;
     if (r.n > 0) {
-        std::vector<MatIn> in(1);
-        in[0].variant = r.variant;
-        in[0].n = r.n;
-        in[0].p = r.p;
-        in[0].kahan = !(S->cfg.flags & PERM_NO_KAHAN);
-        in[0].full = true;
-        Plan pl;
-        plan(S->ctx, in, pl);
-        r.items = pl.items;
-        std::sort(r.items.begin(), r.items.end(),
-                  [](const WaveItem &a, const WaveItem &b) { return a.slot < b.slot; });
-        d.num_parts = pl.mats[0].num_parts;
-        for (WaveItem &it : r.items) {
-            it.mat = (uint32_t)r.slot;
-            it.slot += d.first_part;
+        const int c = r.chunk;
+        const uint64_t T = 1ull << (r.n - 1);
+        if (T >= (64ull << c)) {
+            r.log2L = (uint32_t)c;
+            r.nlanes = 64;
+            r.nitems = (size_t)(T / (64ull << c));
+        } else if (T >= 64) {
+            r.log2L = (uint32_t)(r.n - 1 - 6);
+            r.nlanes = 64;
+            r.nitems = 1;
+        } else {
+            r.log2L = 0;
+            r.nlanes = (uint32_t)T;
+            r.nitems = 1;
         }
+        d.num_parts = (uint32_t)r.nitems;
     }
     r.next = 0;
-    r.work = 0;
-    for (const WaveItem &it : r.items) r.work += item_work(it, r.n);
+    r.work = (double)r.nitems * r.nlanes * std::ldexp(1.0, (int)r.log2L) * r.n;
 }
 
-size_t request_bytes(const perm_ctx *ctx, int variant, int n)
+size_t request_bytes(int variant, int n, int chunk)
 {
     const size_t src_b = align256((size_t)n * n * src_entry_bytes(variant));
     const size_t stg_b = align256(stage_bytes(variant, n));
     size_t parts = 1;
     if (n > 0) {
-        const int c = log2_chunk_for(ctx, variant, n);
         const uint64_t T = 1ull << (n - 1);
-        parts = (size_t)(T >= (64ull << c) ? T / (64ull << c) : 1);
+        parts = (size_t)(T >= (64ull << chunk) ? T / (64ull << chunk) : 1);
     }
     return src_b + stg_b + align256(parts * 16);
 }
@@ -282,13 +302,13 @@ int launch_items(perm_srv *S, const std::vector<WaveItem> &items,
         const uint32_t count = (uint32_t)(j - i);
         const int grid = std::max(1, std::min((int)((count + 3) / 4), occ * S->ctx->num_cus));
         uint64_t adv = 0;
+        unsigned long long *ctr = (unsigned long long *)((char *)S->ctr_dev + 256 * S->cur);
         SRV_HIP((hipError_t)launch_walk(item_variant[i], item_n[i], kahan, fz,
                                         nmax <= FUSED_BUCKETS[0] ? FUSED_BUCKETS[0] : FUSED_BUCKETS[1],
                                         d_items_base + i, count, (const MatDesc *)S->table_dev,
-                                        S->arena_dev, (double *)S->arena_dev,
-                                        (unsigned long long *)S->ctr_dev, S->ctr_value, grid, s,
-                                        &adv));
-        S->ctr_value += adv;
+                                        S->arena_dev, (double *)S->arena_dev, ctr,
+                                        S->ctr_value[S->cur], grid, s, &adv));
+        S->ctr_value[S->cur] += adv;
         i = j;
     }
     return PERM_OK;
@@ -355,9 +375,13 @@ int run_slice(perm_srv *S)
             complete_slice(S, sl, PERM_EDEVICE);
             return PERM_EDEVICE;
         }
+        // throughput between the completions of consecutive slices
+        Slice &other = S->slices[S->cur ^ 1];
         float ms = 0.0f;
-        if (hipEventElapsedTime(&ms, sl.start, sl.done) == hipSuccess && ms > 0.05f && sl.work > 0)
-            S->rate = 0.7 * S->rate + 0.3 * (sl.work / (ms * 1e-3));
+        if (other.busy && hipEventQuery(other.done) == hipSuccess &&
+            hipEventElapsedTime(&ms, sl.done, other.done) == hipSuccess && ms > 0.05f &&
+            other.work > 0)
+            S->rate = 0.7 * S->rate + 0.3 * (other.work / (ms * 1e-3));
         complete_slice(S, sl, PERM_OK);
     }
     std::vector<uint64_t> fresh;
@@ -382,7 +406,7 @@ int run_slice(perm_srv *S)
         double oldest_t = 1e300;
         for (uint64_t t : S->admitted) {
             Req &r = S->reqs[t];
-            if (r.cancel || r.next >= r.items.size()) continue;
+            if (r.cancel || r.next >= r.nitems) continue;
             order.push_back(t);
             if (r.t_submit < oldest_t) { oldest_t = r.t_submit; oldest = t; }
         }
@@ -393,8 +417,8 @@ int run_slice(perm_srv *S)
         double used = 0.0;
         auto take = [&](Req &r, double cap) {
             bool any = false;
-            while (r.next < r.items.size() && used < cap && items.size() < kSliceItems) {
-                const WaveItem &w = r.items[r.next++];
+            while (r.next < r.nitems && used < cap && items.size() < kSliceItems) {
+                const WaveItem w = request_item(r, r.next++);
                 const double wk = item_work(w, r.n);
                 items.push_back(w);
                 iv.push_back(r.variant);
@@ -404,18 +428,18 @@ int run_slice(perm_srv *S)
                 any = true;
             }
             if (any) { r.inflight_slices++; touched.push_back(r.ticket); }
-            if (r.next == r.items.size() && any) { fin.push_back(r.md); fin_t.push_back(r.ticket); }
+            if (r.next == r.nitems && any) { fin.push_back(r.md); fin_t.push_back(r.ticket); }
         };
         if (oldest) take(S->reqs[oldest], budget / 8);
         for (uint64_t t : order) {
             if (used >= budget) break;
-            if (t == oldest && S->reqs[t].next >= S->reqs[t].items.size()) continue;
+            if (t == oldest && S->reqs[t].next >= S->reqs[t].nitems) continue;
             take(S->reqs[t], budget);
         }
         // n = 0 requests (no items): finalize directly
         for (uint64_t t : fresh) {
             Req &r = S->reqs[t];
-            if (r.items.empty() && !r.cancel) {
+            if (r.nitems == 0 && !r.cancel) {
                 fin.push_back(r.md);
                 fin_t.push_back(t);
             }
@@ -423,6 +447,14 @@ int run_slice(perm_srv *S)
     }
     if (fresh.empty() && items.empty() && fin.empty()) return PERM_OK;
     if (items.size() > kSliceItems) return permi::fail(PERM_EINVAL, "slice item overflow");
+    // every item must stay inside its request's Gray range and partial slots
+    for (size_t q = 0; q < items.size(); ++q) {
+        const WaveItem &w = items[q];
+        const uint64_t end = w.x0 + ((uint64_t)w.nlanes << w.log2L);
+        if (in_[q] < 1 || end > (1ull << (in_[q] - 1)) || w.mat >= (uint32_t)S->cfg.max_inflight ||
+            ((size_t)w.slot + 1) * 16 > S->cfg.hbm_budget)
+            return permi::fail(PERM_EINVAL, "server slice item %zu out of range", q);
+    }
 
     // group items: fused-eligible first, then by (variant, n)
     {
@@ -456,16 +488,19 @@ int run_slice(perm_srv *S)
         if (ensure_slice_pinned(sl, need) != PERM_OK) return PERM_ENOMEM;
     }
     char *hp = (char *)sl.pinned;
-    const hipStream_t s = S->stream;
-    SRV_HIP(hipEventRecord(sl.start, s));
-    // device scratch after the two result areas: [new MatDescs][slice 0][slice 1],
-    // each slice region holding its items and its finalize descriptors
+    const hipStream_t s = S->streams[S->cur];
+    Slice &prev = S->slices[S->cur ^ 1];
+    // device scratch after the two result areas: one region per slice with
+    // [new MatDescs][items][finalize MatDescs]
     const size_t mi = (size_t)S->cfg.max_inflight;
-    char *d_new = (char *)S->results_dev + res_b * 2;
-    char *d_slice = d_new + align256(sizeof(MatDesc) * mi) +
-                    (size_t)S->cur * (align256(sizeof(WaveItem) * kSliceItems) +
-                                      align256(sizeof(MatDesc) * mi));
+    const size_t region = align256(sizeof(MatDesc) * mi) + align256(sizeof(WaveItem) * kSliceItems) +
+                          align256(sizeof(MatDesc) * mi);
+    char *d_new = (char *)S->results_dev + res_b * 2 + (size_t)S->cur * region;
+    char *d_slice = d_new + align256(sizeof(MatDesc) * mi);
     char *d_fin = d_slice + align256(sizeof(WaveItem) * kSliceItems);
+    // requests admitted by the previous slice (other stream) must be staged first
+    if (S->prev_done_valid && prev.has_staged) SRV_HIP(hipStreamWaitEvent(s, prev.staged, 0));
+    sl.has_staged = false;
     size_t hoff = 0;
     // 1. new requests: descriptors into the table, matrices into the arena, stage
     if (!fresh.empty()) {
@@ -486,6 +521,8 @@ int run_slice(perm_srv *S)
         SRV_HIP(hipMemcpyAsync(d_new, hp, nb, hipMemcpyHostToDevice, s));
         SRV_HIP((hipError_t)launch_stage((const MatDesc *)d_new, (int)fresh.size(), S->arena_dev,
                                          S->arena_dev, s));
+        SRV_HIP(hipEventRecord(sl.staged, s));
+        sl.has_staged = true;
     }
     // 2. the walk over this slice's items
     if (!items.empty()) {
@@ -501,6 +538,8 @@ int run_slice(perm_srv *S)
         SRV_HIP(hipMemcpyAsync(d_fin, hp + hoff, fb, hipMemcpyHostToDevice, s));
         hoff += align256(fb);
         char *d_res = (char *)S->results_dev + res_b * S->cur;
+        // every earlier slice has finished once the previous one (other stream) has
+        if (S->prev_done_valid) SRV_HIP(hipStreamWaitEvent(s, prev.done, 0));
         SRV_HIP((hipError_t)launch_finalize((const MatDesc *)d_fin, (int)fin.size(),
                                             (const double *)S->arena_dev, d_res, s));
         SRV_HIP(hipMemcpyAsync((char *)sl.pinned + sl.pinned_cap - res_b, d_res, 16 * fin.size(),
@@ -518,6 +557,7 @@ int run_slice(perm_srv *S)
         for (uint64_t t : fresh) S->reqs[t].matrix.clear();
     }
     S->cur ^= 1;
+    S->prev_done_valid = true;
     return PERM_OK;
 }
 
@@ -526,7 +566,7 @@ bool has_work_locked(perm_srv *S)
     if (!S->pending.empty() && !S->free_slots.empty()) return true;
     for (uint64_t t : S->admitted) {
         const Req &r = S->reqs.at(t);
-        if (!r.cancel && r.next < r.items.size()) return true;
+        if (!r.cancel && r.next < r.nitems) return true;
     }
     return false;
 }
@@ -606,7 +646,9 @@ extern "C" int perm_srv_create(perm_ctx *ctx, const perm_srv_cfg *cfg, perm_srv 
         return fail(PERM_EDEVICE, "server setup failed: %s", what);
     };
     if (hipSetDevice(ctx->device) != hipSuccess) return bail("hipSetDevice");
-    if (hipStreamCreateWithFlags(&S->stream, hipStreamNonBlocking) != hipSuccess) return bail("stream");
+    for (int q = 0; q < 2; ++q)
+        if (hipStreamCreateWithFlags(&S->streams[q], hipStreamNonBlocking) != hipSuccess)
+            return bail("stream");
     if (hipMalloc(&S->arena_dev, S->cfg.hbm_budget) != hipSuccess) {
         (void)hipGetLastError();
         perm_srv_destroy(S);
@@ -616,13 +658,14 @@ extern "C" int perm_srv_create(perm_ctx *ctx, const perm_srv_cfg *cfg, perm_srv 
     const size_t mi = (size_t)S->cfg.max_inflight;
     if (hipMalloc(&S->table_dev, sizeof(MatDesc) * mi) != hipSuccess) return bail("table");
     const size_t res_b = 16 * mi;
-    const size_t scratch = res_b * 2 + align256(sizeof(MatDesc) * mi) +
-                           2 * (align256(sizeof(WaveItem) * kSliceItems) + align256(sizeof(MatDesc) * mi));
+    const size_t scratch = res_b * 2 + 2 * (2 * align256(sizeof(MatDesc) * mi) +
+                                            align256(sizeof(WaveItem) * kSliceItems));
     if (hipMalloc(&S->results_dev, scratch) != hipSuccess) return bail("results");
-    if (hipMalloc(&S->ctr_dev, 256) != hipSuccess) return bail("counter");
-    if (hipMemset(S->ctr_dev, 0, 256) != hipSuccess) return bail("counter init");
+    if (hipMalloc(&S->ctr_dev, 512) != hipSuccess) return bail("counter");
+    if (hipMemset(S->ctr_dev, 0, 512) != hipSuccess) return bail("counter init");
     for (Slice &sl : S->slices) {
-        if (hipEventCreate(&sl.done) != hipSuccess || hipEventCreate(&sl.start) != hipSuccess)
+        if (hipEventCreate(&sl.done) != hipSuccess ||
+            hipEventCreateWithFlags(&sl.staged, hipEventDisableTiming) != hipSuccess)
             return bail("events");
         if (ensure_slice_pinned(sl, (size_t)4 << 20) != PERM_OK) return bail("pinned");
     }
@@ -645,7 +688,8 @@ extern "C" int perm_srv_submit(perm_srv *S, const perm_item *item, const void *m
                         : item->field == PERM_F64 ? V_F64
                         : ((S->cfg.flags & PERM_MONTGOMERY) ? V_MONT : V_MODP);
     const size_t mbytes = (size_t)item->n * item->n * src_entry_bytes(variant);
-    const size_t need = request_bytes(S->ctx, variant, item->n);
+    const int chunk = item->n > 0 ? log2_chunk_for(S->ctx, variant, item->n) : 0;
+    const size_t need = request_bytes(variant, item->n, chunk);
     if (need > S->cfg.hbm_budget)
         return fail(PERM_ENOMEM, "request needs %zu device bytes, budget %zu", need, S->cfg.hbm_budget);
     std::lock_guard<std::mutex> lk(S->mu);
@@ -658,6 +702,7 @@ extern "C" int perm_srv_submit(perm_srv *S, const perm_item *item, const void *m
     r.p = item->field == PERM_MODP ? item->p : 0;
     r.matrix.assign((const unsigned char *)matrix, (const unsigned char *)matrix + mbytes);
     r.bytes = need;
+    r.chunk = chunk;
     r.t_submit = now_us();
     *ticket = r.ticket;
     S->reqs.emplace(r.ticket, std::move(r));
@@ -774,16 +819,18 @@ extern "C" void perm_srv_destroy(perm_srv *S)
     }
     if (S->worker.joinable()) S->worker.join();
     (void)hipSetDevice(S->ctx->device);
-    if (S->stream) (void)hipStreamSynchronize(S->stream);
+    for (hipStream_t st : S->streams)
+        if (st) (void)hipStreamSynchronize(st);
     for (Slice &sl : S->slices) {
         if (sl.done) (void)hipEventDestroy(sl.done);
-        if (sl.start) (void)hipEventDestroy(sl.start);
+        if (sl.staged) (void)hipEventDestroy(sl.staged);
         if (sl.pinned) (void)hipHostFree(sl.pinned);
     }
     if (S->arena_dev) (void)hipFree(S->arena_dev);
     if (S->table_dev) (void)hipFree(S->table_dev);
     if (S->results_dev) (void)hipFree(S->results_dev);
     if (S->ctr_dev) (void)hipFree(S->ctr_dev);
-    if (S->stream) (void)hipStreamDestroy(S->stream);
+    for (hipStream_t st : S->streams)
+        if (st) (void)hipStreamDestroy(st);
     delete S;
 }

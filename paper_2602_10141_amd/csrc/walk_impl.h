@@ -549,7 +549,7 @@ __device__ __forceinline__ uint32_t next_item(unsigned long long *ctr, uint64_t 
 // consecutive steps with registers that would cost occupancy.
 template <int V, int N>
 struct Occupancy {
-    static constexpr int regs = V == V_C128 ? 4 * N + 40
+    static constexpr int regs = V == V_C128 ? 4 * N + 56
                               : V == V_MONT ? N + 32
                               : V == V_MODP ? 2 * N + 44
                                             : 2 * N + 32;
@@ -596,7 +596,9 @@ __device__ __forceinline__ void run_fused(std::integer_sequence<int, Ns...>, int
 }
 
 template <int NF, bool KAHAN>
-__global__ __launch_bounds__(BLOCK) void walk_fused(const WaveItem *items, uint32_t count,
+__global__ __launch_bounds__(BLOCK)
+__attribute__((amdgpu_waves_per_eu(Occupancy<V_C128, NF>::waves, 8)))
+void walk_fused(const WaveItem *items, uint32_t count,
                                                     const MatDesc *mats, const char *stage,
                                                     double *partials, unsigned long long *ctr,
                                                     uint64_t base)
