@@ -50,6 +50,38 @@ def sync():
     torch.cuda.synchronize()
 
 
+KERNEL_SOURCES = ["paper_2602_10141_amd/csrc/walk_impl.h", "paper_2602_10141_amd/csrc/walk_common.hip",
+                  "paper_2602_10141_amd/csrc/kernels.h"]
+
+
+def kernel_source_hash():
+    """sha256 over the walk kernel's sources (instantiation files excluded)."""
+    import hashlib
+    h = hashlib.sha256()
+    for f in KERNEL_SOURCES:
+        with open(os.path.join(ROOT, f), "rb") as fh:
+            h.update(fh.read())
+    return h.hexdigest()[:16]
+
+
+def measured_traffic(profile):
+    """HBM bytes per walk launch from a committed counter summary (FETCH_SIZE
+    and WRITE_SIZE passes scaled by a plain copy), or None when the kernel
+    sources changed since the counters were taken."""
+    path = os.path.join(ROOT, "profiles", profile)
+    if not os.path.exists(path):
+        return None
+    vals = {}
+    with open(path) as f:
+        for line in f:
+            if ":" in line and line.split(":")[0].strip() in ("source_hash", "bytes_per_launch"):
+                k, v = line.split(":", 1)
+                vals[k.strip()] = v.strip()
+    if vals.get("source_hash") != kernel_source_hash() or "bytes_per_launch" not in vals:
+        return None
+    return float(vals["bytes_per_launch"])
+
+
 def roofline(ops_per_launch, walk_ms, launches, traffic=None):
     avg_s = walk_ms / max(launches, 1) * 1e-3
     achieved = ops_per_launch / avg_s / 1e12
@@ -147,7 +179,8 @@ def bench_schur(P, ctx, args):
         "config": {"workload": "schur_S28_crt_3primes", "n": n, "primes": primes,
                    "field": "F_p (exact FP64 Barrett walk) + CRT", "terms_per_step": terms,
                    "perm": val},
-        "roofline": roofline(terms * ops_per_term("modp", n), walk_ms, launches),
+        "roofline": roofline(terms * ops_per_term("modp", n), walk_ms, launches,
+                             measured_traffic("traffic_walk_modp_n28_schur_S28_crt.txt")),
     }
     if not args.no_cpu:
         line["cpu_baseline"] = cpu_baseline_schur(n, primes)
@@ -285,22 +318,35 @@ def _serve_run(P, ctx, reqs, rate, seed, slice_us):
     tickets = [None] * len(reqs)
     t0 = time.perf_counter()
 
+    errors = []
+
     def submitter():
         t = t0
-        for i, (A, f, p, _, _) in enumerate(reqs):
-            t += gaps[i]
-            d = t - time.perf_counter()
-            if d > 0:
-                time.sleep(d)
-            tickets[i] = srv.submit(A, f, p)
+        try:
+            for i, (A, f, p, _, _) in enumerate(reqs):
+                t += gaps[i]
+                d = t - time.perf_counter()
+                if d > 0:
+                    time.sleep(d)
+                tickets[i] = srv.submit(A, f, p)
+        except BaseException as e:          # surfaced by the collecting loop
+            errors.append(e)
 
     sub = th.Thread(target=submitter)
     sub.start()
     vals, lats = [None] * len(reqs), [0.0] * len(reqs)
-    for i in range(len(reqs)):
-        while tickets[i] is None:
-            time.sleep(0.0002)
-        vals[i], lats[i] = srv.wait(tickets[i][0], tickets[i][1], timeout_s=600, with_latency=True)
+    try:
+        for i in range(len(reqs)):
+            while tickets[i] is None:
+                if errors:
+                    raise RuntimeError(f"submitting request {i} failed") from errors[0]
+                time.sleep(0.0002)
+            vals[i], lats[i] = srv.wait(tickets[i][0], tickets[i][1], timeout_s=120,
+                                        with_latency=True)
+    except BaseException:
+        srv.close()
+        sub.join()
+        raise
     sub.join()
     wall = time.perf_counter() - t0
     st = srv.stats()

@@ -441,7 +441,9 @@ extern "C" int perm_ctx_create(int device, size_t hbm_budget, perm_ctx **out)
     }
     int rc = ensure(c, c->ctr, 256);
     if (rc != PERM_OK) { perm_ctx_destroy(c); return rc; }
-    if (hipMemset(c->ctr.p, 0, 256) != hipSuccess) {
+    // kernels run on non-blocking streams, which do not order after the null
+    // stream: the counter is zero before the first launch by waiting here
+    if (hipMemset(c->ctr.p, 0, 256) != hipSuccess || hipStreamSynchronize(nullptr) != hipSuccess) {
         perm_ctx_destroy(c);
         return fail(PERM_EDEVICE, "counter init failed");
     }

@@ -367,8 +367,11 @@ void complete_slice(perm_srv *S, Slice &sl, int status)
     S->cv_done.notify_all();
 }
 
-int run_slice(perm_srv *S)
+// Launch the next slice on stream `cur`; *launched tells whether any work
+// went to the device.
+int run_slice(perm_srv *S, bool *launched)
 {
+    *launched = false;
     Slice &sl = S->slices[S->cur];
     if (sl.busy) {
         if (hipEventSynchronize(sl.done) != hipSuccess) {
@@ -385,6 +388,11 @@ int run_slice(perm_srv *S)
         complete_slice(S, sl, PERM_OK);
     }
     std::vector<uint64_t> fresh;
+    // Requests admitted now.  Their nodes stay put while the map rehashes
+    // and none is erased while admitted; only this thread writes the fields
+    // read below, so they are read through these pointers without the lock.
+    // A lookup in S->reqs must hold the lock: submit and poll change the map.
+    std::vector<const Req *> fresh_r;
     std::vector<WaveItem> items;
     std::vector<int> iv, in_;
     std::vector<MatDesc> fin;
@@ -393,10 +401,11 @@ int run_slice(perm_srv *S)
         std::unique_lock<std::mutex> lk(S->mu);
         fresh = admit_locked(S);
         for (uint64_t t : fresh) {
-            Req &r = S->reqs[t];
+            Req &r = S->reqs.at(t);
             layout(S, r);
             r.inflight_slices++;          // held until this slice completes
             touched.push_back(t);
+            fresh_r.push_back(&r);
         }
         // choose items: shortest remaining work first; the oldest request
         // gets at least 1/8 of the budget
@@ -477,7 +486,7 @@ int run_slice(perm_srv *S)
     }
     // pinned layout: [new MatDescs][matrices][items][finalize MatDescs] ... [results]
     size_t mat_bytes = 0;
-    for (uint64_t t : fresh) mat_bytes += align256(S->reqs[t].matrix.size());
+    for (const Req *r : fresh_r) mat_bytes += align256(r->matrix.size());
     const size_t nb = fresh.size() * sizeof(MatDesc);
     const size_t ib = items.size() * sizeof(WaveItem);
     const size_t fb = fin.size() * sizeof(MatDesc);
@@ -504,10 +513,10 @@ int run_slice(perm_srv *S)
     size_t hoff = 0;
     // 1. new requests: descriptors into the table, matrices into the arena, stage
     if (!fresh.empty()) {
-        for (size_t q = 0; q < fresh.size(); ++q) std::memcpy(hp + q * sizeof(MatDesc), &S->reqs[fresh[q]].md, sizeof(MatDesc));
+        for (size_t q = 0; q < fresh_r.size(); ++q) std::memcpy(hp + q * sizeof(MatDesc), &fresh_r[q]->md, sizeof(MatDesc));
         hoff = align256(nb);
-        for (size_t q = 0; q < fresh.size(); ++q) {
-            Req &r = S->reqs[fresh[q]];
+        for (size_t q = 0; q < fresh_r.size(); ++q) {
+            const Req &r = *fresh_r[q];
             if (!r.matrix.empty()) {
                 std::memcpy(hp + hoff, r.matrix.data(), r.matrix.size());
                 SRV_HIP(hipMemcpyAsync((char *)S->arena_dev + r.md.src_off, hp + hoff,
@@ -554,10 +563,11 @@ int run_slice(perm_srv *S)
     {
         std::lock_guard<std::mutex> lk(S->mu);
         S->st.slices++;
-        for (uint64_t t : fresh) S->reqs[t].matrix.clear();
+        for (uint64_t t : fresh) S->reqs.at(t).matrix.clear();
     }
     S->cur ^= 1;
     S->prev_done_valid = true;
+    *launched = true;
     return PERM_OK;
 }
 
@@ -584,13 +594,13 @@ void worker_main(perm_srv *S)
             }
             if (S->busy_since < 0 && (has_work_locked(S) || any_busy)) S->busy_since = now_us();
         }
-        bool work;
+        bool work, launched = false;
         {
             std::lock_guard<std::mutex> lk(S->mu);
             work = has_work_locked(S);
         }
         if (work) {
-            if (run_slice(S) != PERM_OK) {
+            if (run_slice(S, &launched) != PERM_OK) {
                 // fail everything admitted; keep serving new requests
                 std::lock_guard<std::mutex> lk(S->mu);
                 for (uint64_t t : S->admitted) {
@@ -606,9 +616,12 @@ void worker_main(perm_srv *S)
                 }
                 S->admitted.clear();
                 S->cv_done.notify_all();
+                launched = true;
             }
-        } else {
-            // drain the in-flight slices
+        }
+        if (!launched) {
+            // Nothing left to launch, or admission waits for device memory
+            // held by in-flight requests: drain the in-flight slices.
             for (int q = 0; q < 2; ++q) {
                 Slice &sl = S->slices[S->cur];
                 if (sl.busy) {
@@ -662,7 +675,9 @@ extern "C" int perm_srv_create(perm_ctx *ctx, const perm_srv_cfg *cfg, perm_srv 
                                             align256(sizeof(WaveItem) * kSliceItems));
     if (hipMalloc(&S->results_dev, scratch) != hipSuccess) return bail("results");
     if (hipMalloc(&S->ctr_dev, 512) != hipSuccess) return bail("counter");
-    if (hipMemset(S->ctr_dev, 0, 512) != hipSuccess) return bail("counter init");
+    // zeroed before the worker's first launch on the non-blocking streams
+    if (hipMemset(S->ctr_dev, 0, 512) != hipSuccess || hipStreamSynchronize(nullptr) != hipSuccess)
+        return bail("counter init");
     for (Slice &sl : S->slices) {
         if (hipEventCreate(&sl.done) != hipSuccess ||
             hipEventCreateWithFlags(&sl.staged, hipEventDisableTiming) != hipSuccess)

@@ -1,0 +1,142 @@
+// CPU stand-ins for the stage, walk and finalize kernels, for testing the
+// request loop.  Instead of a permanent they move tags: staging stores a hash
+// of the request's matrix, each walk item writes (hash, x0) into its partial
+// slot, and the finalize checks that every slot of the request carries the
+// request's hash and the expected start index, so a skipped, misplaced or
+// stale item is counted.  The walk follows the persistent kernels' work
+// counter protocol exactly: waves take items from a 64-bit counter offset by
+// `base` until the index passes `count`, one extra fetch per wave.
+#include <hip/hip_runtime.h>
+
+#include <algorithm>
+#include <atomic>
+#include <chrono>
+#include <cstdarg>
+#include <cstdio>
+#include <cstdlib>
+#include <thread>
+
+#include "internal.h"
+#include "kernels.h"
+
+using namespace permk;
+
+std::atomic<long> sim_desync{0}, sim_bad_parts{0}, sim_items{0};
+
+uint64_t sim_hash(const unsigned char *p, size_t b)
+{
+    uint64_t h = 1469598103934665603ull;       // FNV-1a
+    for (size_t i = 0; i < b; ++i) {
+        h ^= p[i];
+        h *= 1099511628211ull;
+    }
+    return h;
+}
+
+namespace {
+double ns_per_item()
+{
+    static const double v = getenv("SIM_NS_PER_ITEM") ? atof(getenv("SIM_NS_PER_ITEM")) : 0.0;
+    return v;
+}
+}  // namespace
+
+namespace permk {
+
+int launch_stage(const MatDesc *d_mats, int nmats, const void *src, void *stage, void *stream)
+{
+    sim_enqueue((hipStream_t)stream, [=] {
+        for (int q = 0; q < nmats; ++q) {
+            const MatDesc &d = d_mats[q];
+            const size_t b = (size_t)d.n * d.n * src_entry_bytes(d.variant);
+            *(uint64_t *)((char *)stage + d.stage_off) =
+                sim_hash((const unsigned char *)src + d.src_off, b);
+        }
+    });
+    return 0;
+}
+
+int launch_walk(int, int, bool, bool, int, const WaveItem *d_items, uint32_t count,
+                const MatDesc *d_mats, const void *stage, double *partials,
+                unsigned long long *ctr, uint64_t base, int grid_blocks, void *stream,
+                uint64_t *ctr_advance)
+{
+    *ctr_advance = (uint64_t)count + (uint64_t)grid_blocks * (BLOCK / WAVE);
+    sim_enqueue((hipStream_t)stream, [=] {
+        uint64_t v = *ctr;
+        if (v != base) sim_desync++;
+        long waves = (long)grid_blocks * (BLOCK / WAVE);
+        while (waves > 0) {
+            const uint32_t idx = (uint32_t)(v - base);
+            ++v;
+            if (idx >= count) {
+                --waves;
+                continue;
+            }
+            const WaveItem &w = d_items[idx];
+            const MatDesc &d = d_mats[w.mat];
+            uint64_t *slot = (uint64_t *)((char *)partials + 16 * (size_t)w.slot);
+            slot[0] = *(const uint64_t *)((const char *)stage + d.stage_off);
+            slot[1] = w.x0;
+            sim_items++;
+        }
+        *ctr = v;
+        if (ns_per_item() > 0)
+            std::this_thread::sleep_for(std::chrono::nanoseconds((long)(ns_per_item() * count)));
+    });
+    return 0;
+}
+
+int walk_occupancy(int, int n, bool, bool, int, int *blocks_per_cu)
+{
+    *blocks_per_cu = n > 30 ? 3 : 4;
+    return 0;
+}
+
+int launch_finalize(const MatDesc *d_mats, int nmats, const double *partials, void *out,
+                    void *stream)
+{
+    sim_enqueue((hipStream_t)stream, [=] {
+        for (int q = 0; q < nmats; ++q) {
+            const MatDesc &d = d_mats[q];
+            const uint64_t h = *(const uint64_t *)((const char *)partials + d.stage_off);
+            uint64_t bad = 0;
+            if (d.n > 0) {
+                const uint64_t T = 1ull << (d.n - 1);
+                const uint64_t step = d.num_parts > 1 ? T / d.num_parts : 0;
+                for (uint32_t i = 0; i < d.num_parts; ++i) {
+                    const uint64_t *slot =
+                        (const uint64_t *)((const char *)partials + 16 * (size_t)(d.first_part + i));
+                    if (slot[0] != h || slot[1] != i * step) ++bad;
+                }
+            }
+            sim_bad_parts += (long)bad;
+            uint64_t *o = (uint64_t *)((char *)out + 16 * (size_t)d.out_slot);
+            o[0] = h;
+            o[1] = bad;
+        }
+    });
+    return 0;
+}
+
+}  // namespace permk
+
+namespace permi {
+
+int fail(int code, const char *fmt, ...)
+{
+    va_list ap;
+    va_start(ap, fmt);
+    fprintf(stderr, "error %d: ", code);
+    vfprintf(stderr, fmt, ap);
+    fprintf(stderr, "\n");
+    va_end(ap);
+    return code;
+}
+
+int log2_chunk_for(const perm_ctx *, int, int n)
+{
+    return n <= 20 ? std::max(3, n - 10) : std::min(std::max(n - 27, 10), 20);
+}
+
+}  // namespace permi

@@ -139,6 +139,24 @@ def test_cancel(P, ctx):
         srv.close()
 
 
+def test_budget_held_by_inflight_requests(P, ctx):
+    """Admission that waits for device memory held by requests whose last items
+    are in flight completes those slices first (room for about two requests)."""
+    p = 2147483647
+    reqs = [(E.random_residues(30, p, E.rng(26, i)), "modp", p) for i in range(8)]
+    items, data = P.pack_matrices(reqs)
+    want = P.batch_values(items, P.perm_batch(ctx, items, data))
+    srv = P.Server(ctx, hbm_budget=320 * 1024, slice_us=500)
+    try:
+        tickets = [srv.submit(A, f, q) for A, f, q in reqs]
+        got = [srv.wait(t, it, timeout_s=30) for t, it in tickets]
+        st = srv.stats()
+    finally:
+        srv.close()
+    assert got == want
+    assert st["completed"] == len(reqs)
+
+
 def test_unknown_ticket(P, ctx):
     srv = P.Server(ctx)
     try:
@@ -147,3 +165,20 @@ def test_unknown_ticket(P, ctx):
         assert e.value.status == P.PERM_ENOTFOUND
     finally:
         srv.close()
+
+
+def test_config5_stream_matches_batch(P, ctx):
+    """All 530 geodesic and Schur requests of the serving workload, submitted
+    at once and as a paced stream: every result equals perm_batch's."""
+    import bench
+    reqs = bench.serve_requests(P)
+    mats = [(A, f, p) for A, f, p, _, _ in reqs]
+    items, data = P.pack_matrices(mats)
+    want = P.batch_values(items, P.perm_batch(ctx, items, data))
+    want2 = P.batch_values(items, P.perm_batch(ctx, items, data))
+    assert want == want2
+    for rate in (None, 400.0):
+        got, _, _, _ = bench._serve_run(P, ctx, reqs, rate, 7, 2000.0)
+        bad = [(i, reqs[i][3], reqs[i][4], got[i], want[i]) for i in range(len(reqs))
+               if got[i] != want[i]]
+        assert not bad, f"{len(bad)} served results differ, first: {bad[:5]}"
