@@ -11,7 +11,8 @@ Other workloads (--workload): single14 (one 14x14 Haar unitary, c128),
 haar20 (50,000 Haar U(20) c128 and 50,000 Haar O(20) f64 in one persistent
 launch each), ragged (10,000 GUE/GOE/real and complex Ginibre matrices,
 n uniform in 8..24, one fused launch), serve (Poisson-arrival geodesic and
-Schur requests through the request loop; p50/p99 latency).
+Schur requests through the request loop; p50/p99 latency), schur_odd (exact
+perm(S_n) for odd n through checkpointed CRT jobs with a redundant prime).
 
 Prints one JSON line.  The oracle (CPU Ryser) is timed on a bounded prefix of
 the same computation for the "cpu_baseline" field.
@@ -411,7 +412,60 @@ def bench_copycal(P, ctx, args):
                        "bytes_written": nbytes, "copies": reps}}
 
 
-WORKLOADS = {"copycal": bench_copycal, "serve": bench_serve, "schur28": bench_schur, "single14": bench_single14, "haar20": bench_haar20,
+# wall times the paper reports for exact perm(S_n) on its GPU (Sec. 2.3)
+PAPER_SCHUR_MINUTES = {37: 4.2, 39: 23.0, 41: 88.0, 43: 424.0}
+
+
+def bench_schur_odd(P, ctx, args):
+    """Exact perm(S_n) for odd n through checkpointed jobs over the smallest
+    sufficient primes plus `extra` redundant ones; every k-subset of the
+    residues must lift to the same integer (no table of known values is
+    used)."""
+    import itertools
+    ns = [int(x) for x in args.n_list.split(",")]
+    runs, tot_terms, tot_s, tot_ops = [], 0, 0.0, 0
+    P.perm_prof_enable(ctx, True)
+    P.perm_prof_read(ctx)
+    for n in ns:
+        k = len(P.perm_schur_primes(n))
+        primes = P.perm_schur_primes(n, extra=args.extra)
+        mats = np.stack([P.perm_schur_residues(n, p) for p in primes])
+        bound = (n / 2) * math.log2(n)
+        ck = os.path.join(args.checkpoint_dir, f"schur_S{n}.ckpt") if args.checkpoint_dir else None
+        t0 = time.perf_counter()
+        with P.Job(ctx, mats, primes, bound, checkpoint=ck) as job:
+            while True:
+                done, total = job.run(seconds=20.0)
+                print(f"S_{n}: {done}/{total} pieces, {time.perf_counter() - t0:.1f} s",
+                      file=sys.stderr, flush=True)
+                if done == total:
+                    break
+            val, res = job.result()
+        dt = time.perf_counter() - t0
+        lifts = {P.perm_crt_lift([res[i] for i in sub], [primes[i] for i in sub], bound)
+                 for sub in itertools.combinations(range(len(primes)), k)}
+        assert lifts == {val}, f"S_{n}: prime subsets disagree"
+        assert val != 0 and abs(val) <= n ** (n / 2)
+        terms = len(primes) * (1 << (n - 1))
+        run = {"n": n, "primes": primes, "needed": k, "wall_s": dt, "terms": terms,
+               "terms_per_s": terms / dt, "perm": str(val), "residues": res}
+        if n in PAPER_SCHUR_MINUTES:
+            run["paper_minutes"] = PAPER_SCHUR_MINUTES[n]
+        runs.append(run)
+        tot_terms += terms
+        tot_s += dt
+        tot_ops += terms * ops_per_term("modp", n)
+    walk_ms, launches = P.perm_prof_read(ctx)
+    P.perm_prof_enable(ctx, False)
+    return {"metric": METRIC, "value": tot_terms / tot_s, "unit": "subset-terms/s",
+            "ms_per_step": tot_s * 1e3, "dtype": "f64",
+            "config": {"workload": "schur_odd_exact_crt", "n": ns, "extra_primes": args.extra,
+                       "field": "F_p (exact FP64 Barrett walk) + CRT, checkpointed pieces"},
+            "roofline": roofline(tot_ops / max(launches, 1), walk_ms, launches, None),
+            "runs": runs}
+
+
+WORKLOADS = {"schur_odd": bench_schur_odd, "copycal": bench_copycal, "serve": bench_serve, "schur28": bench_schur, "single14": bench_single14, "haar20": bench_haar20,
              "ragged": bench_ragged}
 
 
@@ -423,10 +477,15 @@ def main():
     ap.add_argument("--workload", default="schur28", choices=sorted(WORKLOADS))
     ap.add_argument("--count", type=int, default=50000)
     ap.add_argument("--no-cpu", action="store_true", help="skip the oracle CPU baseline")
+    ap.add_argument("--n-list", default="29,31,33,35,37,39",
+                    help="schur_odd: odd orders to run")
+    ap.add_argument("--extra", type=int, default=1, help="schur_odd: redundant primes")
+    ap.add_argument("--checkpoint-dir", default=None,
+                    help="schur_odd: keep (and resume from) checkpoints here")
     args = ap.parse_args()
     if args.gpus != 1:
-        print(f"bench.py runs on one GPU only (asked for {args.gpus}); the path shards by "
-              "Gray-index range or by prime, see DESIGN.md", file=sys.stderr)
+        print(f"bench.py runs on one GPU only (asked for {args.gpus}); the path would shard "
+              "by Gray-index range or by prime", file=sys.stderr)
         sys.exit(2)
     if args.workload == "ragged" and args.count == 50000:
         args.count = 10000

@@ -170,6 +170,41 @@ int perm_schur_residues(int n, uint32_t p, uint32_t *out);
 int perm_crt_lift(const uint32_t *residues, const uint32_t *primes, int k, double log2_bound,
                   uint64_t *limbs, int max_limbs, int *nlimbs, int *sign);
 
+/* -------------------------------------------------------- checkpointed job
+ * An exact integer permanent from k residue matrices (as perm_crt_int) for
+ * runs too long for one call: the Glynn index range [0, 2^(n-1)) of every
+ * prime is cut into pieces of 2^piece_log2 indices, each piece's unscaled
+ * partial sum mod p (perm_range) is appended to a checkpoint file as soon as
+ * it is known, and a job created on an existing file resumes where it
+ * stopped.  Pieces of all primes run together in one persistent launch per
+ * batch.  The result is exact and independent of the piece size and of how
+ * often the run was interrupted (paper Sec. 2.1 and 2.3: CRT over primes
+ * and the multi-hour exact runs).
+ *
+ * perm_job_create: mats host, k x n x n uint32 (entries < p_i), copied.
+ *   primes distinct odd primes < 2^31 with product M > 2^(log2_bound + 1).
+ *   piece_log2 in [10, n - 1] (0: n - 9, at least 10).  checkpoint_path NULL
+ *   or "": no file.  A file that exists must have been written for the same
+ *   (n, primes, matrices, piece_log2), else PERM_EINVAL; a torn last line
+ *   (no newline, from a write cut short) is cut off the file.  The file is
+ *   held open for appending.
+ * perm_job_run: runs batches of pieces until all are done or `seconds` of
+ *   wall time have passed (at least one batch); *done / *total receive the
+ *   piece counts (either may be NULL).  Every finished batch is on disk
+ *   (fflush + fsync) before it returns.
+ * perm_job_result: residues (k, may be NULL) and the signed integer as in
+ *   perm_crt_int; PERM_EAGAIN while pieces remain.
+ * Errors: PERM_EINVAL, PERM_ERANGE, PERM_ENOMEM, PERM_EDEVICE; file errors
+ * are PERM_EINVAL with the reason in perm_last_error. */
+typedef struct perm_job perm_job;
+int perm_job_create(perm_ctx *ctx, const uint32_t *mats, const uint32_t *primes, int k, int n,
+                    double log2_bound, int piece_log2, const char *checkpoint_path,
+                    perm_job **out);
+int perm_job_run(perm_job *job, double seconds, uint64_t *done, uint64_t *total);
+int perm_job_result(perm_job *job, uint32_t *residues, uint64_t *limbs, int max_limbs,
+                    int *nlimbs, int *sign);
+void perm_job_destroy(perm_job *job);
+
 /* ------------------------------------------------------------ tuning table
  * The work partition of a permanent: each wavefront item covers 64 lanes x
  * 2^log2_chunk Gray indices.  The table maps (field, n) to log2_chunk; it

@@ -9,6 +9,7 @@
 
 #include "../../include/perm.h"
 #include "kernels.h"
+#include "numth.h"
 
 namespace permi {
 
@@ -84,4 +85,10 @@ int begin_call(perm_ctx *ctx, hipStream_t s);
 int end_call(perm_ctx *ctx, hipStream_t s);
 int execute(perm_ctx *ctx, Plan &pl, const void *src, void *out, size_t out_slots, hipStream_t s);
 int validate_plan(const perm_ctx *ctx, const Plan &pl, size_t out_slots);
+int variant_of(int field, unsigned flags);
+int source_on_device(perm_ctx *ctx, const void *data, size_t bytes, unsigned flags, hipStream_t s,
+                     const void **dev);
+int check_primes(const uint32_t *primes, int k, double log2_bound);
+int write_limbs(const permh::BigU &mag, int sgn, uint64_t *limbs, int max_limbs, int *nlimbs,
+                int *sign);
 }  // namespace permi

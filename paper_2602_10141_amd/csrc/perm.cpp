@@ -475,7 +475,7 @@ extern "C" void perm_ctx_destroy(perm_ctx *c)
 // ---------------------------------------------------------- argument checks
 static bool modulus_ok(uint32_t p) { return p >= 3 && (p & 1u) && p < (1u << 31); }
 
-static int variant_of(int field, unsigned flags)
+int permi::variant_of(int field, unsigned flags)
 {
     switch (field) {
     case PERM_C128: return V_C128;
@@ -487,7 +487,7 @@ static int variant_of(int field, unsigned flags)
 
 // Bring the matrices to the device: returns the device pointer to use as the
 // staging source.
-static int source_on_device(perm_ctx *ctx, const void *data, size_t bytes, unsigned flags,
+int permi::source_on_device(perm_ctx *ctx, const void *data, size_t bytes, unsigned flags,
                             hipStream_t s, const void **dev)
 {
     if (flags & PERM_DEVICE_PTRS) {
@@ -666,7 +666,7 @@ extern "C" int perm_range(perm_ctx *ctx, const perm_item *item, const void *data
 }
 
 // --------------------------------------------------------------------- CRT
-static int write_limbs(const permh::BigU &mag, int sgn, uint64_t *limbs, int max_limbs,
+int permi::write_limbs(const permh::BigU &mag, int sgn, uint64_t *limbs, int max_limbs,
                        int *nlimbs, int *sign)
 {
     if ((int)mag.limb.size() > max_limbs)
@@ -677,7 +677,7 @@ static int write_limbs(const permh::BigU &mag, int sgn, uint64_t *limbs, int max
     return PERM_OK;
 }
 
-static int check_primes(const uint32_t *primes, int k, double log2_bound)
+int permi::check_primes(const uint32_t *primes, int k, double log2_bound)
 {
     if (!primes || k < 1) return fail(PERM_EINVAL, "need k >= 1 primes");
     for (int i = 0; i < k; ++i) {

@@ -78,6 +78,10 @@ _SIGS = {
     "perm_autotune": ([_P, _I, _I, _I, _I], _I),
     "perm_tune_save": ([_P, ctypes.c_char_p], _I),
     "perm_tune_load": ([_P, ctypes.c_char_p], _I),
+    "perm_job_create": ([_P, _P, _P, _I, _I, _D, _I, ctypes.c_char_p, _P], _I),
+    "perm_job_run": ([_P, _D, _P, _P], _I),
+    "perm_job_result": ([_P, _P, _P, _I, _P, _P], _I),
+    "perm_job_destroy": ([_P], None),
     "perm_srv_create": ([_P, _P, _P], _I),
     "perm_srv_submit": ([_P, _P, _P, _P], _I),
     "perm_srv_poll": ([_P, _U64, _P, _P, _P], _I),
@@ -380,6 +384,50 @@ def perm_tune_save(ctx, path):
 
 def perm_tune_load(ctx, path):
     _check(lib().perm_tune_load(ctx.ptr, str(path).encode()))
+
+
+# ------------------------------------------------------- checkpointed job
+class Job:
+    """Exact integer permanent from k residue matrices, run in pieces whose
+    partial sums go to `checkpoint` (resumed if the file exists)."""
+
+    def __init__(self, ctx, mats, primes, log2_bound: float, piece_log2=0, checkpoint=None):
+        m = np.ascontiguousarray(mats, dtype=np.uint32)
+        p = np.ascontiguousarray(primes, dtype=np.uint32)
+        if m.ndim != 3 or m.shape[0] != len(p) or m.shape[1] != m.shape[2]:
+            raise ValueError("mats must have shape (k, n, n) with k = len(primes)")
+        self.k = len(p)
+        self.ptr = ctypes.c_void_p()
+        path = str(checkpoint).encode() if checkpoint else None
+        _check(lib().perm_job_create(ctx.ptr, m.ctypes.data, p.ctypes.data, len(p), m.shape[1],
+                                     float(log2_bound), int(piece_log2), path,
+                                     ctypes.byref(self.ptr)))
+
+    def run(self, seconds=1e30):
+        """Run pieces for about `seconds` (at least one batch); (done, total)."""
+        d, t = ctypes.c_uint64(), ctypes.c_uint64()
+        _check(lib().perm_job_run(self.ptr, float(seconds), ctypes.byref(d), ctypes.byref(t)))
+        return d.value, t.value
+
+    def result(self):
+        """(integer, residues); PermError(PERM_EAGAIN) while pieces remain."""
+        limbs = np.zeros(64, dtype=np.uint64)
+        nl, sg = ctypes.c_int(), ctypes.c_int()
+        res = np.zeros(self.k, dtype=np.uint32)
+        _check(lib().perm_job_result(self.ptr, res.ctypes.data, limbs.ctypes.data, len(limbs),
+                                     ctypes.byref(nl), ctypes.byref(sg)))
+        return _limbs_to_int(limbs, nl.value, sg.value), [int(r) for r in res]
+
+    def close(self):
+        if self.ptr:
+            lib().perm_job_destroy(self.ptr)
+            self.ptr = ctypes.c_void_p()
+
+    def __enter__(self):
+        return self
+
+    def __exit__(self, *exc):
+        self.close()
 
 
 # ----------------------------------------------------------------- serving
