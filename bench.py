@@ -12,7 +12,9 @@ haar20 (50,000 Haar U(20) c128 and 50,000 Haar O(20) f64 in one persistent
 launch each), ragged (10,000 GUE/GOE/real and complex Ginibre matrices,
 n uniform in 8..24, one fused launch), serve (Poisson-arrival geodesic and
 Schur requests through the request loop; p50/p99 latency), schur_odd (exact
-perm(S_n) for odd n through checkpointed CRT jobs with a redundant prime).
+perm(S_n) for odd n through checkpointed CRT jobs with a redundant prime),
+stats (50,000 Haar U(n) and O(n) permanents per odd n in 7..23 and their
+distribution checks).
 
 Prints one JSON line.  The oracle (CPU Ryser) is timed on a bounded prefix of
 the same computation for the "cpu_baseline" field.
@@ -36,12 +38,15 @@ PEAK_FP64_FLOPS = 78.6e12                    # FMA counted twice
 HOST_THREADS = 16                            # CPU share of one GPU on the box
 
 
-def ops_per_term(field: str, n: int, kahan: bool = True) -> int:
-    """Algorithmic FP64 VALU instructions per Glynn term (one lane, one step)."""
-    if field == "c128":        # 2n flip adds + 4(n-1) complex-product ops + Kahan
-        return 2 * n + 4 * (n - 1) + (8 if kahan else 2)
-    if field == "f64":         # n flip adds + (n-1) products + Kahan
-        return n + (n - 1) + (4 if kahan else 1)
+def ops_per_term(field: str, n: int, kahan: bool = True) -> float:
+    """Algorithmic FP64 VALU instructions per Glynn term (one lane, one step).
+    Floats: four consecutive terms are combined as (t0 - t1) + (t2 - t3) (3
+    adds) and enter the compensated sum once (4 ops; 1 without Kahan), per
+    real component."""
+    if field == "c128":        # 2n flip adds + 4(n-1) complex-product ops + group sum
+        return 2 * n + 4 * (n - 1) + 2 * ((3 + (4 if kahan else 1)) / 4)
+    if field == "f64":         # n flip adds + (n-1) products + group sum
+        return n + (n - 1) + (3 + (4 if kahan else 1)) / 4
     # F_p, exact Barrett in binary64: n flip adds + 6 per modular product + 1 accumulate
     return n + 6 * (n - 1) + 1
 
@@ -121,7 +126,7 @@ def cpu_baseline_schur(n, primes, seconds=12.0):
     # one permanent = 2^n Ryser subsets on the CPU = 2^(n-1) Glynn terms in the metric
     value = ryser_subsets_per_s / (1 << n) * (1 << (n - 1))
     return {"value": value, "unit": "subset-terms/s (Glynn-term equivalents)", "cores": threads,
-            "kind": "oracle",
+            "kind": "oracle", "value_1thread": rate1 / 2,
             "sample": f"oracle Ryser mod p on S_{n}: first {per_thread - 1} of 2^{n} subsets per "
                       f"thread, {threads} threads in {dt:.1f} s; rate scaled to 2^{n - 1} terms "
                       f"per permanent"}
@@ -148,6 +153,7 @@ def cpu_baseline_many(mats, field, seconds=10.0):
         th.join()
     dt = time.perf_counter() - t
     return {"value": sum(done) / dt, "unit": "perms/s", "cores": threads, "kind": "oracle",
+            "value_1thread": 1.0 / per,
             "sample": f"oracle Ryser on {sum(done)} of the {field} matrices ({threads} threads, "
                       f"{dt:.1f} s)"}
 
@@ -238,6 +244,9 @@ def bench_haar20(P, ctx, args):
         terms = count * (1 << (n - 1))
         out[name] = {"perms_per_s": count / dt, "terms_per_s": terms / dt, "ms": dt * 1e3,
                      "roofline": roofline(terms * ops_per_term(field, n), walk_ms, launches)}
+        one = per_matrix_launches(P, ctx, items, d, 2000)
+        one["batched_speedup"] = out[name]["perms_per_s"] / one["perms_per_s"]
+        out[name]["one_launch_per_matrix"] = one
     line = {"metric": METRIC, "value": out["c128"]["terms_per_s"], "unit": "subset-terms/s",
             "ms_per_step": out["c128"]["ms"] + out["f64"]["ms"], "dtype": "f64",
             "config": {"workload": "haar20_batched", "count": count, "n": n},
@@ -245,6 +254,54 @@ def bench_haar20(P, ctx, args):
     if not args.no_cpu:
         line["cpu_baseline"] = cpu_baseline_many(U[:4000], "Haar U(20) c128")
     return line
+
+
+def per_matrix_launches(P, ctx, items, d, sample):
+    """The same matrices through one library call (stage, walk, finalize
+    launches) per matrix, device pointers, results left on the device: the
+    comparator for the batched form.  The chunk length of each (field, n) is
+    first autotuned for a single matrix, so the comparator runs in its own
+    best configuration.  Returns perms/s over the first `sample` items and
+    the summed walk-kernel time per matrix."""
+    import ctypes
+    import torch
+    sample = min(sample, len(items))
+    names = {P.PERM_C128: "c128", P.PERM_F64: "f64"}
+    shapes = sorted({(int(it["field"]), int(it["n"])) for it in items[:sample]})
+    for f, n in shapes:
+        P.perm_autotune(ctx, names[f], n, n, batch=1)
+    chunks = {f"{names[f]}{n}": P.perm_tune_get(ctx, names[f], n)[0] for f, n in shapes}
+    out = torch.zeros((sample, 2), dtype=torch.float64, device="cuda")
+    base, optr = d.data_ptr(), out.data_ptr()
+    st = P._stream(None)
+    fns = {P.PERM_C128: P.lib().perm_c128, P.PERM_F64: P.lib().perm_f64}
+
+    def run(lo, hi):
+        for i in range(lo, hi):
+            it = items[i]
+            rc = fns[int(it["field"])](ctx.ptr, ctypes.c_void_p(base + int(it["offset"])),
+                                       int(it["n"]), ctypes.c_void_p(optr + 16 * i),
+                                       P.PERM_DEVICE_PTRS, st)
+            if rc != P.PERM_OK:
+                raise P.PermError(rc, "per-matrix call failed")
+
+    run(0, min(sample, 64))
+    sync()
+    P.perm_prof_enable(ctx, True)
+    P.perm_prof_read(ctx)
+    t0 = time.perf_counter()
+    run(0, sample)
+    sync()
+    dt = time.perf_counter() - t0
+    walk_ms, _ = P.perm_prof_read(ctx)
+    P.perm_prof_enable(ctx, False)
+    for f, n in shapes:
+        P.perm_tune_set(ctx, names[f], n, 0)          # back to the library default
+    out = {"perms_per_s": sample / dt, "sample": sample,
+           "walk_ms_per_matrix": walk_ms / sample, "wall_ms_per_matrix": dt * 1e3 / sample}
+    if len(chunks) <= 4:
+        out["log2_chunk"] = chunks
+    return out
 
 
 def ragged_inputs(count, seed=4):
@@ -287,10 +344,12 @@ def bench_ragged(P, ctx, args):
     P.perm_prof_enable(ctx, False)
     terms = sum(1 << (m[0].shape[0] - 1) for m in mats)
     ops = sum((1 << (m[0].shape[0] - 1)) * ops_per_term(m[1], m[0].shape[0]) for m in mats)
+    one = per_matrix_launches(P, ctx, items, d, 2000)
+    one["batched_speedup"] = len(mats) / dt / one["perms_per_s"]
     return {"metric": METRIC, "value": len(mats) / dt, "unit": "perms/s", "ms_per_step": dt * 1e3,
             "dtype": "f64", "config": {"workload": "ragged_gaussian_n8_24", "count": len(mats),
                                        "terms": terms},
-            "roofline": roofline(ops, walk_ms, launches)}
+            "roofline": roofline(ops, walk_ms, launches), "one_launch_per_matrix": one}
 
 
 def serve_requests(P):
@@ -307,6 +366,23 @@ def serve_requests(P):
             reqs.append((P.perm_schur_residues(n, p), "modp", p, "schur", n))
     order = E.rng(5, 0).permutation(len(reqs))
     return [reqs[i] for i in order]
+
+
+SERVE_FLOAT_CHUNK = 9
+
+
+def serve_tuning(P, ctx, on=True):
+    """Serving favours latency: the geodesic orders get wave items of at most
+    64 x 2^9 indices (a walk of about 0.1 ms) through the context's tuning
+    table, which perm_batch on the same context then shares, so that served
+    and batched results stay bit-identical.  on=False restores the
+    defaults."""
+    for n in range(11, 26, 2):
+        if on:
+            c = P.perm_tune_get(ctx, "c128", n)[0]
+            P.perm_tune_set(ctx, "c128", n, min(c, SERVE_FLOAT_CHUNK))
+        else:
+            P.perm_tune_set(ctx, "c128", n, 0)
 
 
 def _serve_run(P, ctx, reqs, rate, seed, slice_us):
@@ -362,6 +438,7 @@ def _pcts(x):
 
 def bench_serve(P, ctx, args):
     reqs = serve_requests(P)
+    serve_tuning(P, ctx)
     terms = sum(1 << (r[0].shape[0] - 1) for r in reqs)
     slice_us = 2000.0
     _serve_run(P, ctx, reqs[:40], None, 0, slice_us)                 # warm-up
@@ -388,7 +465,8 @@ def bench_serve(P, ctx, args):
     return {"metric": METRIC, "value": terms / wall, "unit": "subset-terms/s",
             "ms_per_step": wall * 1e3, "dtype": "f64",
             "config": {"workload": "serve_geodesic_c128_and_schur_modp", "requests": len(reqs),
-                       "terms": terms, "slice_us": slice_us},
+                       "terms": terms, "slice_us": slice_us,
+                       "c128_log2_chunk_max": SERVE_FLOAT_CHUNK},
             "latency": result}
 
 
@@ -410,6 +488,65 @@ def bench_copycal(P, ctx, args):
             "ms_per_step": dt * 1e3, "dtype": "f64",
             "config": {"workload": "copy_calibration", "bytes_read": nbytes,
                        "bytes_written": nbytes, "copies": reps}}
+
+
+def haar_statistics(pu, po, n):
+    """Distribution checks of the paper's Sec. 3 and 5 on batched outputs:
+    pu = perm of Haar U(n) samples (complex), po = perm of Haar O(n) samples."""
+    from scipy import stats
+    m2 = np.abs(pu) ** 2
+    exact = math.factorial(n) * math.factorial(n - 1) / math.factorial(2 * n - 1)
+    u = {"mean_abs2": float(m2.mean()), "exact_mean_abs2": exact,
+         "mean_abs2_z": float((m2.mean() - exact) / (m2.std(ddof=1) / math.sqrt(len(m2)))),
+         "var_ratio_re_im": float(pu.real.std() / pu.imag.std()),
+         "corr_re_im": float(np.corrcoef(pu.real, pu.imag)[0, 1]),
+         "ks_p_exp": float(stats.kstest(m2 / m2.mean(), "expon").pvalue),
+         "ks_p_phase": float(stats.kstest((np.angle(pu) + np.pi) / (2 * np.pi), "uniform").pvalue),
+         "weibull_shape": float(stats.weibull_min.fit(np.abs(pu), floc=0)[0])}
+    o = {"var": float(po.var(ddof=1)), "excess_kurtosis": float(stats.kurtosis(po)),
+         "mean": float(po.mean())}
+    return u, o
+
+
+def bench_stats(P, ctx, args):
+    """Haar U(n) (c128) and O(n) (f64) permanents, 50,000 samples per n for
+    odd n in 7..23 as in the paper's Sec. 3-5, one batched launch per
+    ensemble and n; throughput per n and the distribution checks."""
+    import torch
+    from paper_2602_10141_amd import ensembles as E
+    count = args.count
+    runs, tot_s, tot_perms = [], 0.0, 0
+    for n in (7, 11, 13, 17, 19, 23):
+        row = {"n": n, "count": count}
+        vals = {}
+        for name, gen, field, cfg in (("U", E.haar_unitary, "c128", 40), ("O", E.haar_orthogonal, "f64", 41)):
+            M = gen(n, E.rng(cfg, n), count=count)
+            items, data = P.pack_matrices([(m, field, 0) for m in M])
+            d = torch.from_numpy(data).cuda()
+            res = torch.zeros((count, 2), dtype=torch.float64, device="cuda")
+            P.perm_batch(ctx, items, d, out=res)
+            sync()
+            P.perm_prof_enable(ctx, True)
+            P.perm_prof_read(ctx)
+            t0 = time.perf_counter()
+            P.perm_batch(ctx, items, d, out=res)
+            sync()
+            dt = time.perf_counter() - t0
+            walk_ms, launches = P.perm_prof_read(ctx)
+            P.perm_prof_enable(ctx, False)
+            r = res.cpu().numpy()
+            vals[name] = r[:, 0] + 1j * r[:, 1] if field == "c128" else r[:, 0]
+            terms = count * (1 << (n - 1))
+            row[name] = {"perms_per_s": count / dt, "ms": dt * 1e3,
+                         "roofline": roofline(terms * ops_per_term(field, n), walk_ms, launches)}
+            tot_s += dt
+            tot_perms += count
+        row["U"]["stats"], row["O"]["stats"] = haar_statistics(vals["U"], vals["O"], n)
+        runs.append(row)
+    return {"metric": METRIC, "value": tot_perms / tot_s, "unit": "perms/s",
+            "ms_per_step": tot_s * 1e3, "dtype": "f64",
+            "config": {"workload": "haar_U_O_statistics_n7_23", "count": count},
+            "runs": runs}
 
 
 # wall times the paper reports for exact perm(S_n) on its GPU (Sec. 2.3)
@@ -465,7 +602,7 @@ def bench_schur_odd(P, ctx, args):
             "runs": runs}
 
 
-WORKLOADS = {"schur_odd": bench_schur_odd, "copycal": bench_copycal, "serve": bench_serve, "schur28": bench_schur, "single14": bench_single14, "haar20": bench_haar20,
+WORKLOADS = {"stats": bench_stats, "schur_odd": bench_schur_odd, "copycal": bench_copycal, "serve": bench_serve, "schur28": bench_schur, "single14": bench_single14, "haar20": bench_haar20,
              "ragged": bench_ragged}
 
 

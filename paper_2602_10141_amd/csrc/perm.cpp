@@ -123,14 +123,28 @@ static int ensure_pinned(perm_ctx *ctx, size_t bytes)
 // ------------------------------------------------------------------ tuning
 int default_log2_chunk(int variant, int n)
 {
-    // 64 * 2^c indices per wave item.  Up to n = 20 about eight items per
-    // matrix (short walks keep a single small permanent's latency low; these
-    // orders are a small share of any batch's work).  Beyond, c in [10, 20]
-    // keeps the per-lane seed (n^2 work) under 1% of the walk and a matrix
-    // at most 2^20 items.
-    (void)variant;
-    if (n <= 20) return std::max(3, n - 10);
-    return std::min(std::max(n - 27, 10), 20);
+    // 64 * 2^c indices per wave item; the partition (and so the summation
+    // order of float results) depends on (field, n) only, never on what else
+    // is in a batch.  Fitted to a sweep on gfx950 over batches that fill the
+    // device (three primes for F_p, 2,000 to 50,000 matrices for floats):
+    //  * floats: one item per matrix up to n = 13 (c = n - 7: shorter walks
+    //    make the per-lane seed dominate), four items at n = 14, 15 (a
+    //    single permanent's latency), two for n = 16..20 (within 2% of one
+    //    item in batch throughput), c = 12 at n = 21, 22 and 10 beyond;
+    //  * F_p: c = n/2 - 5 up to n = 26 and n/2 - 4 (at most 13) from n = 28,
+    //    so that the per-lane seed (n^2 work) stays near 1% of the walk with
+    //    a few items per resident wave and the host plan stays small, then
+    //    n - 27 (2^20 items per matrix at most); at most 20, so that a
+    //    lane's sum of 2^c residues stays below 2^52.
+    if (n < 8) return 3;
+    if (variant == V_MODP || variant == V_MONT) {
+        const int c = n <= 26 ? n / 2 - 5 : std::min(n / 2 - 4, 13);
+        return std::min(std::max(std::max(c, n - 27), 3), 20);
+    }
+    if (n < 14) return std::max(3, n - 7);
+    if (n < 16) return n - 9;
+    if (n <= 20) return n - 8;
+    return n <= 22 ? 12 : 10;
 }
 
 int log2_chunk_for(const perm_ctx *ctx, int variant, int n)

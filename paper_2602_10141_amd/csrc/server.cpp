@@ -122,6 +122,12 @@ struct Slice {
 };
 
 constexpr size_t kSliceItems = 1 << 17;   // wave items per slice, at most
+// F_p results are exact whatever the partition, so served F_p requests use
+// items of at most 64 x 2^9 indices: a slice is never stuck behind items of
+// a millisecond or more.  (Float requests keep the partition of perm_batch on
+// the same context, whose summation order they reproduce bit for bit; the
+// context's tuning table sets it.)
+constexpr int kServeModpChunk = 9;
 
 WaveItem request_item(const Req &r, size_t i)
 {
@@ -408,8 +414,12 @@ int run_slice(perm_srv *S, bool *launched)
             fresh_r.push_back(&r);
         }
         // choose items: shortest remaining work first; the oldest request
-        // gets at least 1/8 of the budget
+        // gets at least 1/8 of the budget.  A slice also carries at least
+        // `fill` items (while any remain), about two per wave the device
+        // holds: the budget comes from the measured rate, and a rate measured
+        // on slices too small to fill the device would shrink the next ones.
         const double budget = std::max(S->rate * S->cfg.slice_us * 1e-6, 1.0);
+        const size_t fill = (size_t)S->ctx->num_cus * 32;
         std::vector<uint64_t> order;
         uint64_t oldest = 0;
         double oldest_t = 1e300;
@@ -424,9 +434,10 @@ int run_slice(perm_srv *S, bool *launched)
             return x.work != y.work ? x.work < y.work : a < b;
         });
         double used = 0.0;
-        auto take = [&](Req &r, double cap) {
+        auto take = [&](Req &r, double cap, bool to_fill) {
             bool any = false;
-            while (r.next < r.nitems && used < cap && items.size() < kSliceItems) {
+            while (r.next < r.nitems && (used < cap || (to_fill && items.size() < fill)) &&
+                   items.size() < kSliceItems) {
                 const WaveItem w = request_item(r, r.next++);
                 const double wk = item_work(w, r.n);
                 items.push_back(w);
@@ -439,11 +450,11 @@ int run_slice(perm_srv *S, bool *launched)
             if (any) { r.inflight_slices++; touched.push_back(r.ticket); }
             if (r.next == r.nitems && any) { fin.push_back(r.md); fin_t.push_back(r.ticket); }
         };
-        if (oldest) take(S->reqs[oldest], budget / 8);
+        if (oldest) take(S->reqs[oldest], budget / 8, false);
         for (uint64_t t : order) {
-            if (used >= budget) break;
+            if (used >= budget && items.size() >= fill) break;
             if (t == oldest && S->reqs[t].next >= S->reqs[t].nitems) continue;
-            take(S->reqs[t], budget);
+            take(S->reqs[t], budget, true);
         }
         // n = 0 requests (no items): finalize directly
         for (uint64_t t : fresh) {
@@ -703,7 +714,8 @@ extern "C" int perm_srv_submit(perm_srv *S, const perm_item *item, const void *m
                         : item->field == PERM_F64 ? V_F64
                         : ((S->cfg.flags & PERM_MONTGOMERY) ? V_MONT : V_MODP);
     const size_t mbytes = (size_t)item->n * item->n * src_entry_bytes(variant);
-    const int chunk = item->n > 0 ? log2_chunk_for(S->ctx, variant, item->n) : 0;
+    int chunk = item->n > 0 ? log2_chunk_for(S->ctx, variant, item->n) : 0;
+    if (variant == V_MODP || variant == V_MONT) chunk = std::min(chunk, kServeModpChunk);
     const size_t need = request_bytes(variant, item->n, chunk);
     if (need > S->cfg.hbm_budget)
         return fail(PERM_ENOMEM, "request needs %zu device bytes, budget %zu", need, S->cfg.hbm_budget);

@@ -134,9 +134,18 @@ int fail(int code, const char *fmt, ...)
     return code;
 }
 
-int log2_chunk_for(const perm_ctx *, int, int n)
+// the library's default partition rule
+int log2_chunk_for(const perm_ctx *, int variant, int n)
 {
-    return n <= 20 ? std::max(3, n - 10) : std::min(std::max(n - 27, 10), 20);
+    if (n < 8) return 3;
+    if (variant == V_MODP || variant == V_MONT) {
+        const int c = n <= 26 ? n / 2 - 5 : std::min(n / 2 - 4, 13);
+        return std::min(std::max(std::max(c, n - 27), 3), 20);
+    }
+    if (n < 14) return std::max(3, n - 7);
+    if (n < 16) return n - 9;
+    if (n <= 20) return n - 8;
+    return n <= 22 ? 12 : 10;
 }
 
 }  // namespace permi

@@ -174,11 +174,15 @@ def test_config5_stream_matches_batch(P, ctx):
     reqs = bench.serve_requests(P)
     mats = [(A, f, p) for A, f, p, _, _ in reqs]
     items, data = P.pack_matrices(mats)
-    want = P.batch_values(items, P.perm_batch(ctx, items, data))
-    want2 = P.batch_values(items, P.perm_batch(ctx, items, data))
-    assert want == want2
-    for rate in (None, 400.0):
-        got, _, _, _ = bench._serve_run(P, ctx, reqs, rate, 7, 2000.0)
-        bad = [(i, reqs[i][3], reqs[i][4], got[i], want[i]) for i in range(len(reqs))
-               if got[i] != want[i]]
-        assert not bad, f"{len(bad)} served results differ, first: {bad[:5]}"
+    bench.serve_tuning(P, ctx)
+    try:
+        want = P.batch_values(items, P.perm_batch(ctx, items, data))
+        want2 = P.batch_values(items, P.perm_batch(ctx, items, data))
+        assert want == want2
+        for rate in (None, 400.0):
+            got, _, _, _ = bench._serve_run(P, ctx, reqs, rate, 7, 2000.0)
+            bad = [(i, reqs[i][3], reqs[i][4], got[i], want[i]) for i in range(len(reqs))
+                   if got[i] != want[i]]
+            assert not bad, f"{len(bad)} served results differ, first: {bad[:5]}"
+    finally:
+        bench.serve_tuning(P, ctx, on=False)

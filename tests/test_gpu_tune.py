@@ -27,12 +27,35 @@ def test_any_chunk_length_is_correct(P, oracle_lib, c):
     try:
         n = 18
         P.perm_tune_set(ctx, "c128", n, c)
+        P.perm_tune_set(ctx, "f64", n, c)
         P.perm_tune_set(ctx, "modp", n, c)
         A = E.ginibre_complex(n, E.rng(30, c))
+        B = E.ginibre_real(n, E.rng(32, c))
         R = E.random_residues(n, 1073742209, E.rng(31, c))
         assert abs(P.perm_c128(ctx, A) - oracle_lib.native.ryser_c128(A)) <= 1e-10 * scale(A)
+        assert abs(P.perm_f64(ctx, B) - oracle_lib.native.ryser_f64(B)) <= 1e-10 * scale(B)
         assert P.perm_modp(ctx, R, 1073742209) == oracle_lib.native.ryser_modp(R, 1073742209)
         assert P.perm_tune_get(ctx, "c128", n)[0] == c
+    finally:
+        ctx.close()
+
+
+@pytest.mark.parametrize("n", [10, 12, 13, 15])
+def test_many_items_per_small_matrix(P, oracle_lib, n):
+    """Small orders split over many wave items (c = 3), batch and single."""
+    ctx = P.Context(0)
+    try:
+        for f in ("c128", "f64"):
+            P.perm_tune_set(ctx, f, n, 3)
+        mats = [(E.ginibre_complex(n, E.rng(33, n + i)), "c128", 0) for i in range(3)] + \
+               [(E.ginibre_real(n, E.rng(34, n + i)), "f64", 0) for i in range(3)]
+        items, data = P.pack_matrices(mats)
+        got = P.batch_values(items, P.perm_batch(ctx, items, data))
+        for (A, f, _), v in zip(mats, got):
+            want = (oracle_lib.native.ryser_c128 if f == "c128" else oracle_lib.native.ryser_f64)(A)
+            assert abs(v - want) <= 1e-10 * scale(A)
+            single = P.perm_c128(ctx, A) if f == "c128" else P.perm_f64(ctx, A)
+            assert single == v
     finally:
         ctx.close()
 
