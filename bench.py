@@ -166,14 +166,15 @@ def bench_schur(P, ctx, args):
     mats = torch.from_numpy(np.stack([P.perm_schur_residues(n, p) for p in primes])
                             .astype(np.int32)).cuda()
     bound = (n / 2) * math.log2(n)
+    flags = P.PERM_MONTGOMERY if args.montgomery else 0
     for _ in range(args.warmup):
-        val, res = P.perm_crt_int(ctx, mats, primes, bound)
+        val, res = P.perm_crt_int(ctx, mats, primes, bound, flags=flags)
     sync()
     P.perm_prof_enable(ctx, True)
     P.perm_prof_read(ctx)
     t0 = time.perf_counter()
     for _ in range(args.steps):
-        val, res = P.perm_crt_int(ctx, mats, primes, bound)
+        val, res = P.perm_crt_int(ctx, mats, primes, bound, flags=flags)
     sync()
     dt = time.perf_counter() - t0
     walk_ms, launches = P.perm_prof_read(ctx)
@@ -184,9 +185,13 @@ def bench_schur(P, ctx, args):
         "metric": METRIC, "value": terms * args.steps / dt, "unit": "subset-terms/s",
         "ms_per_step": dt / args.steps * 1e3, "dtype": "f64",
         "config": {"workload": "schur_S28_crt_3primes", "n": n, "primes": primes,
-                   "field": "F_p (exact FP64 Barrett walk) + CRT", "terms_per_step": terms,
-                   "perm": val},
+                   "field": ("F_p (32-bit Montgomery walk)" if args.montgomery
+                             else "F_p (exact FP64 Barrett walk)") + " + CRT",
+                   "terms_per_step": terms, "perm": val},
+        # (Montgomery is priced at the Barrett walk's instruction count, so
+        # the two fractions compare throughput directly)
         "roofline": roofline(terms * ops_per_term("modp", n), walk_ms, launches,
+                             None if args.montgomery else
                              measured_traffic("traffic_walk_modp_n28_schur_S28_crt.txt")),
     }
     if not args.no_cpu:
@@ -244,9 +249,10 @@ def bench_haar20(P, ctx, args):
         terms = count * (1 << (n - 1))
         out[name] = {"perms_per_s": count / dt, "terms_per_s": terms / dt, "ms": dt * 1e3,
                      "roofline": roofline(terms * ops_per_term(field, n), walk_ms, launches)}
-        one = per_matrix_launches(P, ctx, items, d, 2000)
-        one["batched_speedup"] = out[name]["perms_per_s"] / one["perms_per_s"]
-        out[name]["one_launch_per_matrix"] = one
+        if not args.no_compare:
+            one = per_matrix_launches(P, ctx, items, d, 2000)
+            one["batched_speedup"] = out[name]["perms_per_s"] / one["perms_per_s"]
+            out[name]["one_launch_per_matrix"] = one
     line = {"metric": METRIC, "value": out["c128"]["terms_per_s"], "unit": "subset-terms/s",
             "ms_per_step": out["c128"]["ms"] + out["f64"]["ms"], "dtype": "f64",
             "config": {"workload": "haar20_batched", "count": count, "n": n},
@@ -344,12 +350,15 @@ def bench_ragged(P, ctx, args):
     P.perm_prof_enable(ctx, False)
     terms = sum(1 << (m[0].shape[0] - 1) for m in mats)
     ops = sum((1 << (m[0].shape[0] - 1)) * ops_per_term(m[1], m[0].shape[0]) for m in mats)
-    one = per_matrix_launches(P, ctx, items, d, 2000)
-    one["batched_speedup"] = len(mats) / dt / one["perms_per_s"]
-    return {"metric": METRIC, "value": len(mats) / dt, "unit": "perms/s", "ms_per_step": dt * 1e3,
+    line = {"metric": METRIC, "value": len(mats) / dt, "unit": "perms/s", "ms_per_step": dt * 1e3,
             "dtype": "f64", "config": {"workload": "ragged_gaussian_n8_24", "count": len(mats),
                                        "terms": terms},
-            "roofline": roofline(ops, walk_ms, launches), "one_launch_per_matrix": one}
+            "roofline": roofline(ops, walk_ms, launches)}
+    if not args.no_compare:
+        one = per_matrix_launches(P, ctx, items, d, 2000)
+        one["batched_speedup"] = len(mats) / dt / one["perms_per_s"]
+        line["one_launch_per_matrix"] = one
+    return line
 
 
 def serve_requests(P):
@@ -614,6 +623,10 @@ def main():
     ap.add_argument("--workload", default="schur28", choices=sorted(WORKLOADS))
     ap.add_argument("--count", type=int, default=50000)
     ap.add_argument("--no-cpu", action="store_true", help="skip the oracle CPU baseline")
+    ap.add_argument("--no-compare", action="store_true",
+                    help="skip the one-launch-per-matrix comparator (profiling runs)")
+    ap.add_argument("--montgomery", action="store_true",
+                    help="schur28: the 32-bit Montgomery F_p walk instead of FP64 Barrett")
     ap.add_argument("--n-list", default="29,31,33,35,37,39",
                     help="schur_odd: odd orders to run")
     ap.add_argument("--extra", type=int, default=1, help="schur_odd: redundant primes")

@@ -85,10 +85,19 @@ int launch_stage(const MatDesc *d_mats, int nmats, const void *src, void *stage,
 // `ctr` is a 64-bit device counter whose value at launch time is `base`; the
 // launch adds exactly count + (waves launched) to it, which is returned in
 // *ctr_advance.
+// Waves claim `grab` consecutive items per atomic (grab >= 1): tiny items
+// would otherwise serialize on the one counter.
 int launch_walk(int variant, int n, bool kahan, bool fused, int nmax_fused,
-                const WaveItem *d_items, uint32_t count, const MatDesc *d_mats,
+                const WaveItem *d_items, uint32_t count, uint32_t grab, const MatDesc *d_mats,
                 const void *stage, double *partials, unsigned long long *ctr,
                 uint64_t base, int grid_blocks, void *stream, uint64_t *ctr_advance);
+
+// Items per atomic claim for items of at most 2^max_log2L steps per lane:
+// enough that one claim is at least 64 lane-steps of walk, at most 16.
+inline uint32_t grab_for(uint32_t max_log2L)
+{
+    return max_log2L >= 6 ? 1u : (max_log2L <= 2 ? 16u : (64u >> max_log2L));
+}
 
 // Largest resident blocks per CU for the walk kernel of (variant, n).
 int walk_occupancy(int variant, int n, bool kahan, bool fused, int nmax_fused, int *blocks_per_cu);

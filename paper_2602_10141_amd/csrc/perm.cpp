@@ -393,7 +393,14 @@ int execute(perm_ctx *ctx, Plan &pl, const void *src, void *out, size_t out_slot
         if (!g.count) continue;
         const int occ = occupancy(ctx, g);
         const int per_cu = ctx->grid_per_cu > 0 ? std::min(ctx->grid_per_cu, occ) : occ;
-        const int blocks_needed = (int)((g.count + (BLOCK / WAVE) - 1) / (BLOCK / WAVE));
+        uint32_t max_l2 = 0;
+        for (uint32_t q = 0; q < g.count; ++q) max_l2 = std::max(max_l2, pl.items[g.first_item + q].log2L);
+        // several items per claim only when there are many more items than
+        // resident waves (a short launch keeps one item per wave)
+        const uint32_t resident = (uint32_t)(per_cu * ctx->num_cus * (BLOCK / WAVE));
+        const uint32_t grab = std::max(1u, std::min(grab_for(max_l2), g.count / (2 * resident)));
+        const uint32_t runs = (g.count + grab - 1) / grab;
+        const int blocks_needed = (int)((runs + (BLOCK / WAVE) - 1) / (BLOCK / WAVE));
         const int grid = std::max(1, std::min(blocks_needed, per_cu * ctx->num_cus));
         uint64_t adv = 0;
         std::pair<hipEvent_t, hipEvent_t> ev{nullptr, nullptr};
@@ -408,7 +415,7 @@ int execute(perm_ctx *ctx, Plan &pl, const void *src, void *out, size_t out_slot
             HIPCHK(hipEventRecord(ev.first, s));
         }
         HIPCHK((hipError_t)launch_walk(g.variant, g.n, g.kahan, g.fused, g.nmax_fused,
-                                       d_items + g.first_item, g.count, d_mats, ctx->stage.p,
+                                       d_items + g.first_item, g.count, grab, d_mats, ctx->stage.p,
                                        (double *)ctx->partials.p,
                                        (unsigned long long *)ctx->ctr.p, ctx->ctr_value, grid, s,
                                        &adv));

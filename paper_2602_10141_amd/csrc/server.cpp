@@ -300,18 +300,26 @@ int launch_items(perm_srv *S, const std::vector<WaveItem> &items,
             while (j < items.size() && item_variant[j] == item_variant[i] && item_n[j] == item_n[i]) ++j;
         }
         int nmax = 0;
-        for (size_t q = i; q < j; ++q) nmax = std::max(nmax, item_n[q]);
+        uint32_t max_l2 = 0;
+        for (size_t q = i; q < j; ++q) {
+            nmax = std::max(nmax, item_n[q]);
+            max_l2 = std::max(max_l2, items[q].log2L);
+        }
+        uint32_t grab = grab_for(max_l2);
         int occ = 1;
         walk_occupancy(item_variant[i], item_n[i], kahan, fz,
                        nmax <= FUSED_BUCKETS[0] ? FUSED_BUCKETS[0] : FUSED_BUCKETS[1], &occ);
         occ = std::max(occ, 1);
         const uint32_t count = (uint32_t)(j - i);
-        const int grid = std::max(1, std::min((int)((count + 3) / 4), occ * S->ctx->num_cus));
+        // several items per claim only when items far outnumber resident waves
+        grab = std::max(1u, std::min(grab, count / (2u * (uint32_t)(occ * S->ctx->num_cus * 4))));
+        const uint32_t runs = (count + grab - 1) / grab;
+        const int grid = std::max(1, std::min((int)((runs + 3) / 4), occ * S->ctx->num_cus));
         uint64_t adv = 0;
         unsigned long long *ctr = (unsigned long long *)((char *)S->ctr_dev + 256 * S->cur);
         SRV_HIP((hipError_t)launch_walk(item_variant[i], item_n[i], kahan, fz,
                                         nmax <= FUSED_BUCKETS[0] ? FUSED_BUCKETS[0] : FUSED_BUCKETS[1],
-                                        d_items_base + i, count, (const MatDesc *)S->table_dev,
+                                        d_items_base + i, count, grab, (const MatDesc *)S->table_dev,
                                         S->arena_dev, (double *)S->arena_dev, ctr,
                                         S->ctr_value[S->cur], grid, s, &adv));
         S->ctr_value[S->cur] += adv;

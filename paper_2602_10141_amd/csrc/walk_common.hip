@@ -187,20 +187,22 @@ int walk_occupancy(int variant, int n, bool kahan, bool fused, int nmax_fused, i
 }
 
 int launch_walk(int variant, int n, bool kahan, bool fused, int nmax_fused, const WaveItem *d_items,
-                uint32_t count, const MatDesc *d_mats, const void *stage, double *partials,
-                unsigned long long *ctr, uint64_t base, int grid_blocks, void *stream,
-                uint64_t *ctr_advance)
+                uint32_t count, uint32_t grab, const MatDesc *d_mats, const void *stage,
+                double *partials, unsigned long long *ctr, uint64_t base, int grid_blocks,
+                void *stream, uint64_t *ctr_advance)
 {
     WalkFn f = pick(variant, n, kahan, fused, nmax_fused);
-    if (!f) return (int)hipErrorInvalidValue;
+    if (!f || grab < 1) return (int)hipErrorInvalidValue;
     if (grid_blocks < 1) grid_blocks = 1;
     const char *st = (const char *)stage;
-    void *args[] = {(void *)&d_items, (void *)&count, (void *)&d_mats, (void *)&st,
+    void *args[] = {(void *)&d_items, (void *)&count, (void *)&grab, (void *)&d_mats, (void *)&st,
                     (void *)&partials, (void *)&ctr, (void *)&base};
     hipError_t e = hipLaunchKernel((const void *)f, dim3(grid_blocks), dim3(BLOCK), args, 0,
                                    (hipStream_t)stream);
     if (e != hipSuccess) return (int)e;
-    *ctr_advance = (uint64_t)count + (uint64_t)grid_blocks * (BLOCK / WAVE);
+    // one claim per run of `grab` items, plus the one failing claim per wave
+    const uint64_t runs = ((uint64_t)count + grab - 1) / grab;
+    *ctr_advance = runs + (uint64_t)grid_blocks * (BLOCK / WAVE);
     return (int)hipGetLastError();
 }
 

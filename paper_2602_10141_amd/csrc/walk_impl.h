@@ -595,22 +595,27 @@ struct Occupancy {
                     : (N > 40 ? 3 : 4);
 };
 
-// Persistent kernel: every wave pulls wave items (largest first, as ordered
-// by the host) until the counter passes `count`.  W > 0 overrides the
-// waves-per-SIMD target (used when tuning the budgets).
+// Persistent kernel: every wave claims runs of `grab` consecutive wave items
+// (largest first, as ordered by the host) until the counter passes the
+// number of runs.  W > 0 overrides the waves-per-SIMD target (used when
+// tuning the budgets).
 template <int V, int N, bool KAHAN, int W = 0>
 __global__ __launch_bounds__(BLOCK)
 __attribute__((amdgpu_waves_per_eu(W > 0 ? W : Occupancy<V, N>::waves, 8)))
-void walk_kernel(const WaveItem *items, uint32_t count,
+void walk_kernel(const WaveItem *items, uint32_t count, uint32_t grab,
                                                      const MatDesc *mats, const char *stage,
                                                      double *partials, unsigned long long *ctr,
                                                      uint64_t base)
 {
     const int lane = threadIdx.x & (WAVE - 1);
-    for (uint32_t idx = next_item(ctr, base, lane); idx < count; idx = next_item(ctr, base, lane)) {
-        const WaveItem it = sload(items + idx);
-        const MatDesc md = sload(mats + it.mat);
-        run_item<typename OpsFor<V, N, KAHAN>::type>(it, md, stage, partials, lane);
+    const uint32_t runs = (uint32_t)(((uint64_t)count + grab - 1) / grab);
+    for (uint32_t r = next_item(ctr, base, lane); r < runs; r = next_item(ctr, base, lane)) {
+        const uint32_t end = (uint32_t)min((uint64_t)count, (uint64_t)(r + 1) * grab);
+        for (uint32_t idx = r * grab; idx < end; ++idx) {
+            const WaveItem it = sload(items + idx);
+            const MatDesc md = sload(mats + it.mat);
+            run_item<typename OpsFor<V, N, KAHAN>::type>(it, md, stage, partials, lane);
+        }
     }
 }
 
@@ -636,23 +641,27 @@ __device__ __forceinline__ void run_fused(std::integer_sequence<int, Ns...>, int
 template <int NF, bool KAHAN>
 __global__ __launch_bounds__(BLOCK)
 __attribute__((amdgpu_waves_per_eu(Occupancy<V_C128, NF>::waves, 8)))
-void walk_fused(const WaveItem *items, uint32_t count,
+void walk_fused(const WaveItem *items, uint32_t count, uint32_t grab,
                                                     const MatDesc *mats, const char *stage,
                                                     double *partials, unsigned long long *ctr,
                                                     uint64_t base)
 {
     const int lane = threadIdx.x & (WAVE - 1);
-    for (uint32_t idx = next_item(ctr, base, lane); idx < count; idx = next_item(ctr, base, lane)) {
-        const WaveItem it = sload(items + idx);
-        const MatDesc md = sload(mats + it.mat);
-        run_fused<KAHAN>(std::make_integer_sequence<int, NF>{}, md.n, md.variant, it, md, stage,
-                         partials, lane);
+    const uint32_t runs = (uint32_t)(((uint64_t)count + grab - 1) / grab);
+    for (uint32_t r = next_item(ctr, base, lane); r < runs; r = next_item(ctr, base, lane)) {
+        const uint32_t end = (uint32_t)min((uint64_t)count, (uint64_t)(r + 1) * grab);
+        for (uint32_t idx = r * grab; idx < end; ++idx) {
+            const WaveItem it = sload(items + idx);
+            const MatDesc md = sload(mats + it.mat);
+            run_fused<KAHAN>(std::make_integer_sequence<int, NF>{}, md.n, md.variant, it, md,
+                             stage, partials, lane);
+        }
     }
 }
 
 // ------------------------------------------------ instantiation tables
-using WalkFn = void (*)(const WaveItem *, uint32_t, const MatDesc *, const char *, double *,
-                        unsigned long long *, uint64_t);
+using WalkFn = void (*)(const WaveItem *, uint32_t, uint32_t, const MatDesc *, const char *,
+                        double *, unsigned long long *, uint64_t);
 
 template <int V, bool K, int LO, int... Ns>
 inline WalkFn walk_fn_range(int n, std::integer_sequence<int, Ns...>)

@@ -57,28 +57,33 @@ int launch_stage(const MatDesc *d_mats, int nmats, const void *src, void *stage,
 }
 
 int launch_walk(int, int, bool, bool, int, const WaveItem *d_items, uint32_t count,
-                const MatDesc *d_mats, const void *stage, double *partials,
+                uint32_t grab, const MatDesc *d_mats, const void *stage, double *partials,
                 unsigned long long *ctr, uint64_t base, int grid_blocks, void *stream,
                 uint64_t *ctr_advance)
 {
-    *ctr_advance = (uint64_t)count + (uint64_t)grid_blocks * (BLOCK / WAVE);
+    if (grab < 1) return 1;
+    const uint64_t runs = ((uint64_t)count + grab - 1) / grab;
+    *ctr_advance = runs + (uint64_t)grid_blocks * (BLOCK / WAVE);
     sim_enqueue((hipStream_t)stream, [=] {
         uint64_t v = *ctr;
         if (v != base) sim_desync++;
         long waves = (long)grid_blocks * (BLOCK / WAVE);
         while (waves > 0) {
-            const uint32_t idx = (uint32_t)(v - base);
+            const uint32_t r = (uint32_t)(v - base);
             ++v;
-            if (idx >= count) {
+            if (r >= runs) {
                 --waves;
                 continue;
             }
-            const WaveItem &w = d_items[idx];
-            const MatDesc &d = d_mats[w.mat];
-            uint64_t *slot = (uint64_t *)((char *)partials + 16 * (size_t)w.slot);
-            slot[0] = *(const uint64_t *)((const char *)stage + d.stage_off);
-            slot[1] = w.x0;
-            sim_items++;
+            const uint64_t end = std::min<uint64_t>(count, (uint64_t)(r + 1) * grab);
+            for (uint64_t idx = (uint64_t)r * grab; idx < end; ++idx) {
+                const WaveItem &w = d_items[idx];
+                const MatDesc &d = d_mats[w.mat];
+                uint64_t *slot = (uint64_t *)((char *)partials + 16 * (size_t)w.slot);
+                slot[0] = *(const uint64_t *)((const char *)stage + d.stage_off);
+                slot[1] = w.x0;
+                sim_items++;
+            }
         }
         *ctr = v;
         if (ns_per_item() > 0)

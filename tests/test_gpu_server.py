@@ -101,7 +101,7 @@ def test_request_larger_than_budget_is_rejected(P, ctx):
 
 
 def test_pending_queue_full(P, ctx):
-    srv = P.Server(ctx, max_pending=2, max_inflight=1, hbm_budget=1 << 22)
+    srv = P.Server(ctx, max_pending=2, max_inflight=1, hbm_budget=1 << 23)
     try:
         big = srv.submit(E.random_residues(34, 2147483647, E.rng(24, 0)), "modp", 2147483647)
         saw_eagain = False
