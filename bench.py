@@ -253,6 +253,11 @@ def bench_haar20(P, ctx, args):
             one = per_matrix_launches(P, ctx, items, d, 2000)
             one["batched_speedup"] = out[name]["perms_per_s"] / one["perms_per_s"]
             out[name]["one_launch_per_matrix"] = one
+            # the same batch handed over in host memory: PCIe copy in and out
+            # included (context only, never the reported value)
+            t0 = time.perf_counter()
+            P.perm_batch(ctx, items, data)
+            out[name]["host_buffers_perms_per_s"] = count / (time.perf_counter() - t0)
     line = {"metric": METRIC, "value": out["c128"]["terms_per_s"], "unit": "subset-terms/s",
             "ms_per_step": out["c128"]["ms"] + out["f64"]["ms"], "dtype": "f64",
             "config": {"workload": "haar20_batched", "count": count, "n": n},
