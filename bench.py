@@ -14,7 +14,7 @@ n uniform in 8..24, one fused launch), serve (Poisson-arrival geodesic and
 Schur requests through the request loop; p50/p99 latency), schur_odd (exact
 perm(S_n) for odd n through checkpointed CRT jobs with a redundant prime),
 stats (50,000 Haar U(n) and O(n) permanents per odd n in 7..23 and their
-distribution checks).
+distribution checks), dft (the DFT-geodesic fingerprint r(n)).
 
 Prints one JSON line.  The oracle (CPU Ryser) is timed on a bounded prefix of
 the same computation for the "cpu_baseline" field.
@@ -454,7 +454,7 @@ def bench_serve(P, ctx, args):
     reqs = serve_requests(P)
     serve_tuning(P, ctx)
     terms = sum(1 << (r[0].shape[0] - 1) for r in reqs)
-    slice_us = 2000.0
+    slice_us = args.slice_us
     _serve_run(P, ctx, reqs[:40], None, 0, slice_us)                 # warm-up
     vals, lats, wall, st = _serve_run(P, ctx, reqs, None, 1, slice_us)
     sat_rate = len(reqs) / wall
@@ -563,6 +563,41 @@ def bench_stats(P, ctx, args):
             "runs": runs}
 
 
+def bench_dft(P, ctx, args):
+    """The DFT-geodesic fingerprint (paper Sec. 4.3): perm(gamma(t)) on a
+    257-point t grid for odd n in 7..23 and both logarithms of -1, one
+    batched launch per branch; r(n) = |perm F_n| / min_t |perm gamma(t)|."""
+    import torch
+    from paper_2602_10141_amd import ensembles as E
+    ns = [7, 9, 11, 13, 15, 17, 19, 21, 23]
+    grid = np.linspace(0.0, 1.0, 257)
+    runs, tot_s, tot = [], 0.0, 0
+    for branch in (1, -1):
+        mats = [(E.dft_geodesic(n, t, branch), "c128", 0) for n in ns for t in grid]
+        items, data = P.pack_matrices(mats)
+        d = torch.from_numpy(data).cuda()
+        res = torch.zeros((len(mats), 2), dtype=torch.float64, device="cuda")
+        P.perm_batch(ctx, items, d, out=res)
+        sync()
+        t0 = time.perf_counter()
+        P.perm_batch(ctx, items, d, out=res)
+        sync()
+        tot_s += time.perf_counter() - t0
+        tot += len(mats)
+        r = res.cpu().numpy()
+        v = (r[:, 0] + 1j * r[:, 1]).reshape(len(ns), len(grid))
+        for i, n in enumerate(ns):
+            a = np.abs(v[i])
+            k = int(a.argmin())
+            runs.append({"n": n, "branch": branch, "r": float(a[-1] / a[k]), "t_min": float(grid[k]),
+                         "abs_perm_F": float(a[-1]), "min_abs_perm": float(a[k]),
+                         "perm_half": [float(v[i][128].real), float(v[i][128].imag)]})
+    return {"metric": METRIC, "value": tot / tot_s, "unit": "perms/s", "ms_per_step": tot_s * 1e3,
+            "dtype": "f64", "config": {"workload": "dft_geodesic_fingerprint", "n": ns,
+                                       "grid_points": len(grid), "branches": [1, -1]},
+            "runs": runs}
+
+
 # wall times the paper reports for exact perm(S_n) on its GPU (Sec. 2.3)
 PAPER_SCHUR_MINUTES = {37: 4.2, 39: 23.0, 41: 88.0, 43: 424.0}
 
@@ -616,7 +651,7 @@ def bench_schur_odd(P, ctx, args):
             "runs": runs}
 
 
-WORKLOADS = {"stats": bench_stats, "schur_odd": bench_schur_odd, "copycal": bench_copycal, "serve": bench_serve, "schur28": bench_schur, "single14": bench_single14, "haar20": bench_haar20,
+WORKLOADS = {"dft": bench_dft, "stats": bench_stats, "schur_odd": bench_schur_odd, "copycal": bench_copycal, "serve": bench_serve, "schur28": bench_schur, "single14": bench_single14, "haar20": bench_haar20,
              "ragged": bench_ragged}
 
 
@@ -628,6 +663,8 @@ def main():
     ap.add_argument("--workload", default="schur28", choices=sorted(WORKLOADS))
     ap.add_argument("--count", type=int, default=50000)
     ap.add_argument("--no-cpu", action="store_true", help="skip the oracle CPU baseline")
+    ap.add_argument("--slice-us", type=float, default=2000.0,
+                    help="serve: device time per slice of the request loop")
     ap.add_argument("--no-compare", action="store_true",
                     help="skip the one-launch-per-matrix comparator (profiling runs)")
     ap.add_argument("--montgomery", action="store_true",

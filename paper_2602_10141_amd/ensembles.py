@@ -24,6 +24,14 @@ Geodesics from I to the n-cycle C_n, (C_n)_{ij} = [i = j+1 mod n] (Sec. 4.1):
 * ``cycle_geodesic_circulant`` the paper's circulant formula, eigen-angles
   2 pi k / n with k = 0..n-1: gamma(t)_{jl} = (e^{2 pi i t} - 1) /
   (n (e^{2 pi i (l - j + t)/n} - 1)).
+
+Geodesic from I to the unitary DFT matrix F_n = (w^{jk} / sqrt n),
+w = e^{2 pi i / n} (Sec. 4.3): ``dft_geodesic``.  F_n^4 = I, so its
+eigenvalues lie in {1, i, -1, -i} and P_lam = (1/4) sum_k lam^{-k} F_n^k
+projects onto the eigenspace of lam.  gamma(t) = sum_lam e^{t log lam} P_lam
+with log 1 = 0, log(+-i) = +-i pi/2 and log(-1) = branch * i pi: the paper
+does not say which logarithm of -1 it takes, so the branch (+1 or -1) is an
+argument.
 """
 import numpy as np
 
@@ -99,6 +107,27 @@ def cycle_geodesic_circulant(n: int, t: float) -> np.ndarray:
     num = np.exp(2j * np.pi * t) - 1.0
     den = n * (np.exp(2j * np.pi * (d + t) / n) - 1.0)
     return num / den
+
+
+def dft_matrix(n: int) -> np.ndarray:
+    """Unitary DFT matrix F_n = (w^{jk} / sqrt n), w = e^{2 pi i / n}."""
+    j = np.arange(n)
+    return np.exp(2j * np.pi * np.outer(j, j) / n) / np.sqrt(n)
+
+
+def dft_geodesic(n: int, t: float, branch: int = 1) -> np.ndarray:
+    """gamma(t) = exp(t log F_n), log(-1) = branch * i pi, complex128."""
+    if branch not in (1, -1):
+        raise ValueError("branch must be +1 or -1")
+    F = dft_matrix(n)
+    powers = [np.eye(n, dtype=complex)]
+    for _ in range(3):
+        powers.append(powers[-1] @ F)
+    out = np.zeros((n, n), dtype=complex)
+    for lam, angle in ((1, 0.0), (1j, np.pi / 2), (-1, branch * np.pi), (-1j, -np.pi / 2)):
+        proj = sum(lam ** (-k) * powers[k] for k in range(4)) / 4
+        out += np.exp(1j * angle * t) * proj
+    return out
 
 
 def geodesic_grid(points: int = 64):

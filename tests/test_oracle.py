@@ -352,6 +352,46 @@ def test_midpoint_asymptotic_n25(O):
     assert abs(v / (2 * math.exp(-n) * (1 + 1 / (3 * n))) - 1) < 2e-3
 
 
+def _dft_geodesic_by_eigh(n, t, branch):
+    """gamma(t) from an orthonormal eigenbasis: H + 2K with H = (F + F^*)/2 and
+    K = (F - F^*)/(2i) is Hermitian with eigenvalue 1, -1, 2, -2 on the
+    eigenspaces of F for 1, -1, i, -i (F is normal and F^4 = I)."""
+    F = E.dft_matrix(n)
+    H = (F + F.conj().T) / 2
+    K = (F - F.conj().T) / 2j
+    mu, V = np.linalg.eigh(H + 2 * K)
+    angle = {1: 0.0, -1: branch * np.pi, 2: np.pi / 2, -2: -np.pi / 2}
+    ph = np.array([np.exp(1j * t * angle[int(round(m))]) for m in mu])
+    return (V * ph) @ V.conj().T
+
+
+@pytest.mark.parametrize("n", [4, 5, 7, 9, 12])
+@pytest.mark.parametrize("branch", [1, -1])
+def test_dft_geodesic_construction(O, n, branch):
+    F = E.dft_matrix(n)
+    assert np.max(np.abs(E.dft_geodesic(n, 0.0, branch) - np.eye(n))) < 1e-13
+    assert np.max(np.abs(E.dft_geodesic(n, 1.0, branch) - F)) < 1e-13
+    for t in (0.13, 0.5, 0.81):
+        G = E.dft_geodesic(n, t, branch)
+        assert np.max(np.abs(G @ G.conj().T - np.eye(n))) < 1e-13      # unitary
+        assert np.max(np.abs(G - _dft_geodesic_by_eigh(n, t, branch))) < 1e-12
+        # one-parameter group: gamma(s) gamma(t) = gamma(s + t)
+        assert np.max(np.abs(E.dft_geodesic(n, 0.3, branch) @ G -
+                             E.dft_geodesic(n, 0.3 + t, branch))) < 1e-12
+    # the two branches differ exactly on the -1 eigenspace
+    if n >= 2:
+        d = E.dft_geodesic(n, 0.5, 1) - E.dft_geodesic(n, 0.5, -1)
+        assert np.max(np.abs(d)) > 0.1
+
+
+def test_dft_permanent_endpoints(O):
+    for n in (3, 5, 6, 7):
+        F = E.dft_matrix(n)
+        assert abs(O.native.ryser_c128(E.dft_geodesic(n, 0.0)) - 1) < 1e-14
+        want = O.reference.bruteforce(F)
+        assert abs(O.native.ryser_c128(E.dft_geodesic(n, 1.0)) - want) < 1e-12
+
+
 def test_branch_phase_relation(O):
     for n in (5, 9):
         for t in (0.2, 0.37, 0.5, 0.9):
