@@ -461,6 +461,8 @@ def bench_serve(P, ctx, args):
     cls = np.array([r[3] for r in reqs])
     result = {"saturation": {"wall_s": wall, "requests_per_s": sat_rate,
                              "terms_per_s": terms / wall, **_pcts(lats),
+                             "slices": st["slices"], "busy_s": st["busy_s"],
+                             "items": st["items"], "rate": st["rate"],
                              "geodesic": _pcts(lats[cls == "geodesic"]),
                              "schur": _pcts(lats[cls == "schur"])}}
     ref = vals
@@ -468,6 +470,8 @@ def bench_serve(P, ctx, args):
         v, l, w, s2 = _serve_run(P, ctx, reqs, f * sat_rate, 2 + int(f * 10), slice_us)
         assert v == ref, "served results differ between runs"
         result[f"load_{f}"] = {"wall_s": w, "offered_per_s": f * sat_rate, **_pcts(l),
+                               "slices": s2["slices"], "busy_s": s2["busy_s"],
+                               "items": s2["items"], "rate": s2["rate"],
                                "geodesic": _pcts(l[cls == "geodesic"]),
                                "schur": _pcts(l[cls == "schur"])}
     # every Schur residue is 0 for even n; geodesic perms are real and |.| <= 1
@@ -663,7 +667,7 @@ def main():
     ap.add_argument("--workload", default="schur28", choices=sorted(WORKLOADS))
     ap.add_argument("--count", type=int, default=50000)
     ap.add_argument("--no-cpu", action="store_true", help="skip the oracle CPU baseline")
-    ap.add_argument("--slice-us", type=float, default=2000.0,
+    ap.add_argument("--slice-us", type=float, default=500.0,
                     help="serve: device time per slice of the request loop")
     ap.add_argument("--no-compare", action="store_true",
                     help="skip the one-launch-per-matrix comparator (profiling runs)")

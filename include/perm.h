@@ -240,7 +240,7 @@ typedef struct {
     size_t hbm_budget;      /* device bytes for admitted requests (0 = 1 GiB) */
     int max_inflight;       /* admitted requests at once (0 = 4096) */
     int max_pending;        /* queued, not yet admitted; submit beyond -> PERM_EAGAIN (0 = 65536) */
-    double slice_us;        /* target GPU time per slice (0 = 2000) */
+    double slice_us;        /* target GPU time per slice in microseconds (0 = 500) */
     unsigned flags;         /* PERM_NO_KAHAN, PERM_MONTGOMERY */
 } perm_srv_cfg;
 
@@ -250,6 +250,9 @@ typedef struct {
     double p50_us, p99_us, mean_us, max_us;   /* submit -> result visible, completed requests */
     double terms;                             /* Glynn terms executed */
     double busy_s;                            /* wall time with work on the device */
+    uint64_t items;                           /* wave items launched (all slices) */
+    double rate;                              /* current calibrated device rate, work units/s
+                                                 (a unit: one lane-step of an order-n walk = n) */
 } perm_srv_stats;
 
 int perm_srv_create(perm_ctx *ctx, const perm_srv_cfg *cfg, perm_srv **out);

@@ -118,16 +118,19 @@ struct Slice {
     std::vector<uint64_t> finishing;     // tickets finalized by this slice
     std::vector<uint64_t> touched;       // tickets with items in this slice
     double work = 0;
+    size_t nitems = 0;
+    double launch_us = 0;                // host time of the launch
     bool busy = false;
 };
 
 constexpr size_t kSliceItems = 1 << 17;   // wave items per slice, at most
 // F_p results are exact whatever the partition, so served F_p requests use
-// items of at most 64 x 2^9 indices: a slice is never stuck behind items of
-// a millisecond or more.  (Float requests keep the partition of perm_batch on
+// items of at most 64 x 2^8 indices (about 0.35 ms of a wave's time at
+// n = 34 with three waves per SIMD): a slice is never stuck behind long
+// items.  (Float requests keep the partition of perm_batch on
 // the same context, whose summation order they reproduce bit for bit; the
 // context's tuning table sets it.)
-constexpr int kServeModpChunk = 9;
+constexpr int kServeModpChunk = 8;
 
 WaveItem request_item(const Req &r, size_t i)
 {
@@ -161,7 +164,8 @@ struct perm_srv {
     std::vector<int> free_slots;
     Slice slices[2];
     int cur = 0;
-    double rate = 2.0e12;                // work units per second, calibrated
+    double rate = 2.0e12;                // work units per second, calibrated (under mu)
+    double last_complete_us = -1.0;      // host time the previous slice was seen done
 
     std::mutex mu;
     std::condition_variable cv_work, cv_done;
@@ -392,13 +396,20 @@ int run_slice(perm_srv *S, bool *launched)
             complete_slice(S, sl, PERM_EDEVICE);
             return PERM_EDEVICE;
         }
-        // throughput between the completions of consecutive slices
-        Slice &other = S->slices[S->cur ^ 1];
-        float ms = 0.0f;
-        if (other.busy && hipEventQuery(other.done) == hipSuccess &&
-            hipEventElapsedTime(&ms, sl.done, other.done) == hipSuccess && ms > 0.05f &&
-            other.work > 0)
-            S->rate = 0.7 * S->rate + 0.3 * (other.work / (ms * 1e-3));
+        // Throughput from the spacing of consecutive completions, sampled only
+        // when this slice was already queued as the previous one finished (so
+        // the device had its work the whole interval) and it carried enough
+        // items to fill the device.  (Measuring against the other stream's
+        // event instead samples only when the two completions happen to be
+        // close together and overestimates the rate.)
+        const double now = now_us();
+        const size_t fill = (size_t)S->ctx->num_cus * 12;
+        if (S->last_complete_us > 0 && sl.launch_us < S->last_complete_us && sl.work > 0 &&
+            sl.nitems >= fill / 2 && now - S->last_complete_us > 20.0) {
+            std::lock_guard<std::mutex> lk(S->mu);
+            S->rate = 0.7 * S->rate + 0.3 * (sl.work / ((now - S->last_complete_us) * 1e-6));
+        }
+        S->last_complete_us = now;
         complete_slice(S, sl, PERM_OK);
     }
     std::vector<uint64_t> fresh;
@@ -423,11 +434,10 @@ int run_slice(perm_srv *S, bool *launched)
         }
         // choose items: shortest remaining work first; the oldest request
         // gets at least 1/8 of the budget.  A slice also carries at least
-        // `fill` items (while any remain), about two per wave the device
-        // holds: the budget comes from the measured rate, and a rate measured
-        // on slices too small to fill the device would shrink the next ones.
+        // `fill` items (while any remain), about one per wave the device
+        // holds, so that no slice leaves compute units idle.
         const double budget = std::max(S->rate * S->cfg.slice_us * 1e-6, 1.0);
-        const size_t fill = (size_t)S->ctx->num_cus * 32;
+        const size_t fill = (size_t)S->ctx->num_cus * 12;
         std::vector<uint64_t> order;
         uint64_t oldest = 0;
         double oldest_t = 1e300;
@@ -578,10 +588,13 @@ int run_slice(perm_srv *S, bool *launched)
     sl.touched = touched;
     sl.work = 0;
     for (size_t q = 0; q < items.size(); ++q) sl.work += item_work(items[q], in_[q]);
+    sl.nitems = items.size();
+    sl.launch_us = now_us();
     sl.busy = true;
     {
         std::lock_guard<std::mutex> lk(S->mu);
         S->st.slices++;
+        S->st.items += items.size();
         for (uint64_t t : fresh) S->reqs.at(t).matrix.clear();
     }
     S->cur ^= 1;
@@ -671,7 +684,7 @@ extern "C" int perm_srv_create(perm_ctx *ctx, const perm_srv_cfg *cfg, perm_srv 
     if (!S->cfg.hbm_budget) S->cfg.hbm_budget = (size_t)1 << 30;
     if (S->cfg.max_inflight <= 0) S->cfg.max_inflight = 4096;
     if (S->cfg.max_pending <= 0) S->cfg.max_pending = 65536;
-    if (!(S->cfg.slice_us > 0)) S->cfg.slice_us = 2000.0;
+    if (!(S->cfg.slice_us > 0)) S->cfg.slice_us = 500.0;
     S->cfg.hbm_budget = align256(S->cfg.hbm_budget);
     auto bail = [&](const char *what) {
         perm_srv_destroy(S);
@@ -834,6 +847,7 @@ extern "C" int perm_srv_get_stats(perm_srv *S, perm_srv_stats *out)
         st.max_us = v.back();
     }
     if (S->busy_since >= 0) st.busy_s += (now_us() - S->busy_since) * 1e-6;
+    st.rate = S->rate;
     *out = st;
     return PERM_OK;
 }

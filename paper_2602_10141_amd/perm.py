@@ -51,7 +51,8 @@ class perm_srv_stats(ctypes.Structure):
                 ("canceled", ctypes.c_uint64), ("slices", ctypes.c_uint64),
                 ("p50_us", ctypes.c_double), ("p99_us", ctypes.c_double),
                 ("mean_us", ctypes.c_double), ("max_us", ctypes.c_double),
-                ("terms", ctypes.c_double), ("busy_s", ctypes.c_double)]
+                ("terms", ctypes.c_double), ("busy_s", ctypes.c_double),
+                ("items", ctypes.c_uint64), ("rate", ctypes.c_double)]
 
 
 _lib = None

@@ -101,7 +101,7 @@ def test_request_larger_than_budget_is_rejected(P, ctx):
 
 
 def test_pending_queue_full(P, ctx):
-    srv = P.Server(ctx, max_pending=2, max_inflight=1, hbm_budget=1 << 23)
+    srv = P.Server(ctx, max_pending=2, max_inflight=1, hbm_budget=1 << 24)
     try:
         big = srv.submit(E.random_residues(34, 2147483647, E.rng(24, 0)), "modp", 2147483647)
         saw_eagain = False
@@ -141,12 +141,12 @@ def test_cancel(P, ctx):
 
 def test_budget_held_by_inflight_requests(P, ctx):
     """Admission that waits for device memory held by requests whose last items
-    are in flight completes those slices first (room for about two requests)."""
+    are in flight completes those slices first (room for one request)."""
     p = 2147483647
     reqs = [(E.random_residues(30, p, E.rng(26, i)), "modp", p) for i in range(8)]
     items, data = P.pack_matrices(reqs)
     want = P.batch_values(items, P.perm_batch(ctx, items, data))
-    srv = P.Server(ctx, hbm_budget=320 * 1024, slice_us=500)
+    srv = P.Server(ctx, hbm_budget=800 * 1024, slice_us=500)
     try:
         tickets = [srv.submit(A, f, q) for A, f, q in reqs]
         got = [srv.wait(t, it, timeout_s=30) for t, it in tickets]

@@ -44,9 +44,9 @@ def run(binary, timeout=240, **env):
 @pytest.mark.parametrize("scenario", [
     dict(rate=0, seed=1),                                   # the whole stream at once
     dict(rate=3000, seed=2, ns_per_item=100),               # paced arrivals, device time
-    dict(rate=0, seed=3, budget_mb=24, ns_per_item=50),     # admission waits for memory
-    dict(rate=0, seed=4, max_inflight=1, budget_mb=20),     # one request at a time
-    dict(rate=0, seed=5, cancel_every=3, budget_mb=24),     # cancellations
+    dict(rate=0, seed=3, budget_mb=40, ns_per_item=50),     # admission waits for memory
+    dict(rate=0, seed=4, max_inflight=1, budget_mb=36),     # one request at a time
+    dict(rate=0, seed=5, cancel_every=3, budget_mb=40),     # cancellations
     dict(rate=0, seed=6, cancel_every=2, max_inflight=3, slice_us=300),
 ], ids=["burst", "paced", "budget", "inflight1", "cancel", "cancel_inflight3"])
 def test_served_results_intact(sim, scenario):
@@ -65,7 +65,7 @@ def test_no_data_races(tmp_path):
     if not os.path.exists(CLANG):
         pytest.skip("clang with ThreadSanitizer not available")
     b = _build(str(tmp_path / "srvsim_tsan"), CLANG, ["-O1", "-fsanitize=thread"])
-    for sc in (dict(rate=0, seed=8), dict(rate=2000, seed=9, cancel_every=4, budget_mb=24)):
+    for sc in (dict(rate=0, seed=8), dict(rate=2000, seed=9, cancel_every=4, budget_mb=40)):
         env = dict(sc, big="26,28,30")
         e = dict(os.environ, TSAN_OPTIONS="halt_on_error=1 exitcode=66")
         e.update({f"SIM_{k.upper()}": str(v) for k, v in env.items()})
