@@ -88,14 +88,27 @@ def measured_traffic(profile):
     return float(vals["bytes_per_launch"])
 
 
-def roofline(ops_per_launch, walk_ms, launches, traffic=None):
+def flops_per_op(field: str, n: int) -> float:
+    """FP64 flops per algorithmic instruction (an FMA counts two) of the walk."""
+    if field == "c128":        # 2(n-1) of the 4(n-1) product instructions are FMAs
+        return (ops_per_term("c128", n) + 2 * (n - 1)) / ops_per_term("c128", n)
+    if field == "f64":
+        return 1.0
+    return (ops_per_term("modp", n) + 2 * (n - 1) - (n - 1)) / ops_per_term("modp", n)   # 2 FMAs, 1 rint
+
+
+def roofline(ops_per_launch, walk_ms, launches, traffic=None, flops_ratio=None):
     avg_s = walk_ms / max(launches, 1) * 1e-3
     achieved = ops_per_launch / avg_s / 1e12
     peak = PEAK_LANE_OPS / 1e12
-    return {"bound": "alu", "achieved": round(achieved, 3), "peak": round(peak, 3),
-            "unit": "Tlane-op/s (FP64 VALU)", "frac": round(achieved / peak, 4),
-            "traffic": traffic, "kernel_avg_ms": round(avg_s * 1e3, 4),
-            "launches": launches}
+    out = {"bound": "alu", "achieved": round(achieved, 3), "peak": round(peak, 3),
+           "unit": "Tlane-op/s (FP64 VALU)", "frac": round(achieved / peak, 4),
+           "traffic": traffic, "kernel_avg_ms": round(avg_s * 1e3, 4),
+           "launches": launches}
+    if flops_ratio is not None:
+        out["tflops"] = round(achieved * flops_ratio, 3)
+        out["tflops_of_78_6"] = round(achieved * flops_ratio / (PEAK_FP64_FLOPS / 1e12), 4)
+    return out
 
 
 # ---------------------------------------------------------------- CPU baseline
@@ -192,7 +205,8 @@ def bench_schur(P, ctx, args):
         # the two fractions compare throughput directly)
         "roofline": roofline(terms * ops_per_term("modp", n), walk_ms, launches,
                              None if args.montgomery else
-                             measured_traffic("traffic_walk_modp_n28_schur_S28_crt.txt")),
+                             measured_traffic("traffic_walk_modp_n28_schur_S28_crt.txt"),
+                             flops_per_op("modp", n)),
     }
     if not args.no_cpu:
         line["cpu_baseline"] = cpu_baseline_schur(n, primes)
@@ -248,7 +262,8 @@ def bench_haar20(P, ctx, args):
         P.perm_prof_enable(ctx, False)
         terms = count * (1 << (n - 1))
         out[name] = {"perms_per_s": count / dt, "terms_per_s": terms / dt, "ms": dt * 1e3,
-                     "roofline": roofline(terms * ops_per_term(field, n), walk_ms, launches)}
+                     "roofline": roofline(terms * ops_per_term(field, n), walk_ms, launches,
+                                          None, flops_per_op(field, n))}
         if not args.no_compare:
             one = per_matrix_launches(P, ctx, items, d, 2000)
             one["batched_speedup"] = out[name]["perms_per_s"] / one["perms_per_s"]

@@ -203,6 +203,8 @@ int plan(perm_ctx *ctx, const std::vector<MatIn> &in, Plan &pl)
     int nmax = 0;
     for (size_t m = 0; m < in.size(); ++m) {
         const MatIn &a = in[m];
+        if (a.variant < 0 || a.variant >= V_COUNT || a.n < 0 || a.n > NMAX)
+            return fail(PERM_EINVAL, "plan: matrix %zu has variant %d, n = %d", m, a.variant, a.n);
         if (a.variant != in[0].variant || a.n != in[0].n) same = false;
         if (a.variant == V_MONT || a.kahan != in[0].kahan) fusable = false;
         nmax = std::max(nmax, a.n);
@@ -262,6 +264,10 @@ int plan(perm_ctx *ctx, const std::vector<MatIn> &in, Plan &pl)
         d.out_slot = a.out_slot;
         if (a.n > 0) pl.stage_bytes += (stage_bytes(a.variant, a.n) + 255) & ~(size_t)255;
     }
+    // chunk length per (variant, n), looked up once per call
+    int chunk[V_COUNT][NMAX + 1];
+    for (auto &row : chunk)
+        for (int &c : row) c = -1;
     // items per group, each group sorted largest first (stable)
     for (size_t g = 0; g < groups.size(); ++g) {
         Group gd = gdesc[g];
@@ -270,7 +276,8 @@ int plan(perm_ctx *ctx, const std::vector<MatIn> &in, Plan &pl)
         for (uint32_t m : groups[g]) {
             const MatIn &a = in[m];
             MatDesc &d = pl.mats[m];
-            const int c = log2_chunk_for(ctx, a.variant, a.n);
+            int &c = chunk[a.variant][a.n];
+            if (c < 0) c = log2_chunk_for(ctx, a.variant, a.n);
             const uint64_t T = 1ull << (a.n - 1);
             const uint64_t x0 = a.full ? 0 : a.x0;
             const uint64_t x1 = a.full ? T : a.x1;
