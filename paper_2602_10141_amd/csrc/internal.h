@@ -74,6 +74,10 @@ struct perm_ctx {
     std::map<int, int> occ;
     bool prof_on = false;
     std::vector<std::pair<hipEvent_t, hipEvent_t>> prof_pending, prof_pool;
+    // host scratch reused across calls (keeps its capacity: large batches
+    // would otherwise fault in fresh pages on every call)
+    std::vector<permi::MatIn> scratch_in;
+    permi::Plan scratch_plan;
 };
 
 namespace permi {

@@ -189,7 +189,8 @@ extern "C" int perm_job_run(perm_job *J, double seconds, uint64_t *done, uint64_
         if (rc != PERM_OK) return rc;
         const void *src = nullptr;
         if ((rc = source_on_device(ctx, J->mats.data(), per * J->k, 0, s, &src)) != PERM_OK) return rc;
-        std::vector<MatIn> in(pick.size());
+        std::vector<MatIn> &in = ctx->scratch_in;
+        in.assign(pick.size(), MatIn{});
         for (size_t q = 0; q < pick.size(); ++q) {
             MatIn &m = in[q];
             m.variant = variant;
@@ -202,7 +203,7 @@ extern "C" int perm_job_run(perm_job *J, double seconds, uint64_t *done, uint64_
             m.x1 = m.x0 + (1ull << J->piece_log2);
             m.no_scale = true;
         }
-        Plan pl;
+        Plan &pl = ctx->scratch_plan;
         if ((rc = plan(ctx, in, pl)) != PERM_OK) return rc;
         if ((rc = ensure(ctx, ctx->outs, pick.size() * 16)) != PERM_OK) return rc;
         if ((rc = execute(ctx, pl, src, ctx->outs.p, pick.size(), s)) != PERM_OK) return rc;

@@ -164,8 +164,9 @@ static void split_range(uint64_t x0, uint64_t x1, int c, uint32_t mat, uint32_t 
 {
     nparts = 0;
     while (x0 < x1) {
-        int e = x0 ? __builtin_ctzll(x0) : 63;
-        while (e > 0 && (e >= 64 || x0 + (1ull << e) > x1)) --e;
+        // the largest aligned power-of-two block at x0 that fits in [x0, x1)
+        const int fit = 63 - __builtin_clzll(x1 - x0);
+        const int e = x0 ? std::min(__builtin_ctzll(x0), fit) : fit;
         const uint64_t B = 1ull << e;
         const uint64_t wave = 64ull << c;
         auto push = [&](uint64_t xs, uint32_t log2L, uint32_t lanes) {
@@ -213,7 +214,18 @@ int plan(perm_ctx *ctx, const std::vector<MatIn> &in, Plan &pl)
 
     std::vector<std::vector<uint32_t>> groups;   // matrix ids per launch
     std::vector<Group> gdesc;
-    if (same || !fusable) {
+    if (same && !in.empty() && in[0].n > 0) {
+        // one specialized launch over every matrix
+        std::vector<uint32_t> ids(in.size());
+        for (size_t m = 0; m < in.size(); ++m) ids[m] = (uint32_t)m;
+        groups.push_back(std::move(ids));
+        Group g{};
+        g.variant = in[0].variant;
+        g.n = in[0].n;
+        g.kahan = in[0].kahan;
+        g.fused = false;
+        gdesc.push_back(g);
+    } else if (same || !fusable) {
         std::map<std::pair<int, int>, size_t> gi;
         for (size_t m = 0; m < in.size(); ++m) {
             if (in[m].n == 0) continue;                     // no walk needed
@@ -272,7 +284,8 @@ int plan(perm_ctx *ctx, const std::vector<MatIn> &in, Plan &pl)
     for (size_t g = 0; g < groups.size(); ++g) {
         Group gd = gdesc[g];
         gd.first_item = (uint32_t)pl.items.size();
-        std::vector<WaveItem> gi;
+        std::vector<WaveItem> &gi = pl.items;            // the group's items are appended
+        const size_t g0 = gi.size();
         for (uint32_t m : groups[g]) {
             const MatIn &a = in[m];
             MatDesc &d = pl.mats[m];
@@ -288,22 +301,23 @@ int plan(perm_ctx *ctx, const std::vector<MatIn> &in, Plan &pl)
             pl.nparts += np;
         }
         // largest first (stable): key = indices per item x n
-        std::vector<std::pair<uint64_t, uint32_t>> key(gi.size());
+        const size_t cnt = gi.size() - g0;
+        auto work = [&](const WaveItem &w) {
+            return ((uint64_t)w.nlanes << w.log2L) * (uint64_t)in[w.mat].n;
+        };
         bool uniform = true;
-        for (size_t q = 0; q < gi.size(); ++q) {
-            key[q] = {((uint64_t)gi[q].nlanes << gi[q].log2L) * (uint64_t)in[gi[q].mat].n, (uint32_t)q};
-            uniform = uniform && key[q].first == key[0].first;
-        }
+        for (size_t q = 1; q < cnt && uniform; ++q) uniform = work(gi[g0 + q]) == work(gi[g0]);
         if (!uniform) {
+            std::vector<std::pair<uint64_t, uint32_t>> key(cnt);
+            for (size_t q = 0; q < cnt; ++q) key[q] = {work(gi[g0 + q]), (uint32_t)q};
             std::stable_sort(key.begin(), key.end(),
                              [](const std::pair<uint64_t, uint32_t> &a,
                                 const std::pair<uint64_t, uint32_t> &b) { return a.first > b.first; });
-            std::vector<WaveItem> sorted(gi.size());
-            for (size_t q = 0; q < gi.size(); ++q) sorted[q] = gi[key[q].second];
-            gi.swap(sorted);
+            std::vector<WaveItem> sorted(cnt);
+            for (size_t q = 0; q < cnt; ++q) sorted[q] = gi[g0 + key[q].second];
+            std::copy(sorted.begin(), sorted.end(), gi.begin() + g0);
         }
-        pl.items.insert(pl.items.end(), gi.begin(), gi.end());
-        gd.count = (uint32_t)gi.size();
+        gd.count = (uint32_t)cnt;
         pl.groups.push_back(gd);
     }
     return PERM_OK;
@@ -548,7 +562,7 @@ static int single(perm_ctx *ctx, int variant, const void *A, int n, uint32_t p, 
     in[0].p = p;
     in[0].kahan = !(flags & PERM_NO_KAHAN);
     in[0].full = true;
-    Plan pl;
+    Plan &pl = ctx->scratch_plan;
     if ((rc = plan(ctx, in, pl)) != PERM_OK) return rc;
     if ((rc = ensure(ctx, ctx->outs, 256)) != PERM_OK) return rc;
     if ((rc = execute(ctx, pl, src, ctx->outs.p, 1, s)) != PERM_OK) return rc;
@@ -623,7 +637,8 @@ extern "C" int perm_batch(perm_ctx *ctx, const perm_item *items, int count, cons
     if (rc != PERM_OK) return rc;
     const void *src = nullptr;
     if ((rc = source_on_device(ctx, data, span, flags, s, &src)) != PERM_OK) return rc;
-    std::vector<MatIn> in(count);
+    std::vector<MatIn> &in = ctx->scratch_in;
+    in.assign(count, MatIn{});
     for (int i = 0; i < count; ++i) {
         in[i].variant = variant_of(items[i].field, flags);
         in[i].n = items[i].n;
@@ -633,7 +648,7 @@ extern "C" int perm_batch(perm_ctx *ctx, const perm_item *items, int count, cons
         in[i].kahan = !(flags & PERM_NO_KAHAN);
         in[i].full = true;
     }
-    Plan pl;
+    Plan &pl = ctx->scratch_plan;
     if ((rc = plan(ctx, in, pl)) != PERM_OK) return rc;
     void *dout = out;
     if (!(flags & PERM_DEVICE_PTRS)) {
@@ -677,7 +692,7 @@ extern "C" int perm_range(perm_ctx *ctx, const perm_item *item, const void *data
     in[0].x0 = x0;
     in[0].x1 = x1;
     in[0].no_scale = true;
-    Plan pl;
+    Plan &pl = ctx->scratch_plan;
     if ((rc = plan(ctx, in, pl)) != PERM_OK) return rc;
     if ((rc = ensure(ctx, ctx->outs, 256)) != PERM_OK) return rc;
     if (x0 == x1) {
@@ -751,7 +766,8 @@ extern "C" int perm_crt_int(perm_ctx *ctx, const uint32_t *mats, const uint32_t 
     const size_t per = (size_t)n * n * 4;
     const void *src = nullptr;
     if ((rc = source_on_device(ctx, mats, per * k, flags, s, &src)) != PERM_OK) return rc;
-    std::vector<MatIn> in(k);
+    std::vector<MatIn> &in = ctx->scratch_in;
+    in.assign(k, MatIn{});
     for (int i = 0; i < k; ++i) {
         in[i].variant = variant;
         in[i].n = n;
@@ -760,7 +776,7 @@ extern "C" int perm_crt_int(perm_ctx *ctx, const uint32_t *mats, const uint32_t 
         in[i].out_slot = (uint32_t)i;
         in[i].full = true;
     }
-    Plan pl;
+    Plan &pl = ctx->scratch_plan;
     if ((rc = plan(ctx, in, pl)) != PERM_OK) return rc;
     if ((rc = ensure(ctx, ctx->outs, (size_t)k * 16)) != PERM_OK) return rc;
     if ((rc = execute(ctx, pl, src, ctx->outs.p, (size_t)k, s)) != PERM_OK) return rc;

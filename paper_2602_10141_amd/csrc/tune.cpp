@@ -101,7 +101,7 @@ extern "C" int perm_autotune(perm_ctx *ctx, int field, int n_lo, int n_hi, int b
         const int c_hi = small ? cmax : std::min(cmax, cdef + 4);
         for (int c = c_lo; c <= c_hi; ++c) {
             ctx->tune[{field, n}] = perm_tune{c, 0};
-            Plan pl;
+            Plan &pl = ctx->scratch_plan;
             if ((rc = plan(ctx, in, pl)) != PERM_OK) { ctx->tune = saved; return rc; }
             float ms = 0.0f;
             if ((rc = time_plan(ctx, pl, ctx->src.p, ctx->outs.p, (size_t)count, reps, &ms)) != PERM_OK) {
