@@ -10,6 +10,7 @@
 #include <unistd.h>
 
 #include <chrono>
+#include <cmath>
 #include <cinttypes>
 #include <cstdio>
 #include <cstring>
@@ -173,10 +174,15 @@ extern "C" int perm_job_run(perm_job *J, double seconds, uint64_t *done, uint64_
     hipStream_t s = ctx->stream;
     const size_t per = (size_t)J->n * J->n * 4;
     const int variant = variant_of(PERM_MODP, 0);
-    // a batch of about 2^37 Glynn terms (near a second on one device), at
-    // least one piece
-    const uint64_t batch_pieces =
-        J->piece_log2 >= 37 ? 1 : std::min<uint64_t>(4096, 1ull << (37 - J->piece_log2));
+    // A batch covers at least 2^37 Glynn terms (about a second on one
+    // device) and at least 8 wave items per resident wave (about 12 per
+    // compute unit), so that the last round of long items does not leave
+    // most of the device idle.
+    const int c = log2_chunk_for(ctx, variant, J->n);
+    const double items_min = 8.0 * 12.0 * ctx->num_cus;
+    const double terms = std::max(std::ldexp(1.0, 37), items_min * std::ldexp(1.0, c + 6));
+    const double want = std::ceil(terms / std::ldexp(1.0, J->piece_log2));
+    const uint64_t batch_pieces = (uint64_t)std::min(4096.0, std::max(1.0, want));
     while (J->done < all) {
         std::vector<std::pair<uint32_t, uint64_t>> pick;      // (prime, piece)
         for (uint64_t scan = 0; scan < all && pick.size() < batch_pieces; ++scan) {

@@ -581,16 +581,17 @@ __device__ __forceinline__ uint32_t next_item(unsigned long long *ctr, uint64_t 
 // budgets come from a sweep on gfx950: a larger budget lets the scheduler
 // overlap consecutive steps with registers that cost occupancy, a smaller one
 // makes it spill the row sums around the per-item seed.  c128 runs best at 3
-// waves for n = 20..28; F_p (Barrett) at 3 waves from n = 21 on and F_p
-// (Montgomery) at 4 compile without spills and run as fast as any setting
-// measured; f64 gains more from occupancy (7 waves at n = 20) than it loses
-// to a few spilled registers.
+// waves for n = 20..28; F_p (Barrett) runs at 3 waves from n = 21 up to 48
+// (the walk loop stays free of spills; from n = 36 the per-item seed
+// spills, once per item) and F_p (Montgomery) at 4 compiles without spills;
+// both run as fast as any setting measured; f64 gains more from occupancy
+// (7 waves at n = 20) than it loses to a few spilled registers.
 template <int V, int N>
 struct Occupancy {
     static constexpr int clamp(int w) { return w < 1 ? 1 : (w > 8 ? 8 : w); }
     static constexpr int waves =
         V == V_C128 ? clamp(512 / (4 * N + 56))
-      : V == V_MODP ? (N > 40 ? 2 : N > 20 ? 3 : N > 12 ? 4 : clamp(512 / (2 * N + 44)))
+      : V == V_MODP ? (N > 20 ? 3 : N > 12 ? 4 : clamp(512 / (2 * N + 44)))
       : V == V_F64  ? clamp(512 / (2 * N + 32))
                     : (N > 40 ? 3 : 4);
 };
