@@ -35,7 +35,7 @@ import numpy as np  # noqa: E402
 METRIC = "Ryser subset-terms/s (c128, F_p) n=20–36; batched perms/s; served p50/p99"
 PEAK_LANE_OPS = 256 * 4 * 16 * 2.4e9        # FP64 VALU lane-ops/s: 256 CUs x 4 SIMD16 x 2.4 GHz
 PEAK_FP64_FLOPS = 78.6e12                    # FMA counted twice
-HOST_THREADS = 16                            # CPU share of one GPU on the box
+HOST_THREADS = 16                            # host threads for the oracle baseline (one GPU's CPU share)
 
 
 def ops_per_term(field: str, n: int, kahan: bool = True) -> float:
