@@ -53,7 +53,7 @@ def run_batch_device(P, ctx, mats):
 
 
 @pytest.mark.parametrize("kind", ["unitary", "orthogonal"])
-def test_config3_haar20_50000(P, ctx, oracle_lib, kind):
+def test_haar20_batch_50000(P, ctx, oracle_lib, kind):
     n, count = 20, 50000
     if kind == "unitary":
         M = E.haar_unitary(n, E.rng(3, 0), count=count)
@@ -69,7 +69,7 @@ def test_config3_haar20_50000(P, ctx, oracle_lib, kind):
         assert abs(vals[i] - w) <= TOL * scale(M[i]), (i, vals[i], w)
 
 
-def test_config4_ragged_10000(P, ctx, oracle_lib):
+def test_ragged_batch_10000(P, ctx, oracle_lib):
     import bench
     mats = bench.ragged_inputs(10000)
     vals = run_batch_device(P, ctx, mats)
@@ -92,7 +92,7 @@ def test_config4_ragged_10000(P, ctx, oracle_lib):
             assert abs(vals[i].imag) <= TOL * scale(A)
 
 
-def test_config5_geodesic_512(P, ctx, oracle_lib):
+def test_serving_geodesic_points_512(P, ctx, oracle_lib):
     reqs = [(E.cycle_geodesic(n, t), "c128", 0) for n in range(11, 26, 2) for t in E.geodesic_grid(64)]
     vals = run_batch_device(P, ctx, reqs)
     grid = E.geodesic_grid(64)
@@ -110,7 +110,7 @@ def test_config5_geodesic_512(P, ctx, oracle_lib):
 
 
 @pytest.mark.parametrize("n", [32, 34, 36])
-def test_config5_schur_even(P, ctx, oracle_lib, n):
+def test_serving_schur_orders_32_to_36(P, ctx, oracle_lib, n):
     import torch
     primes = P.perm_schur_primes(n, extra=6 - len(P.perm_schur_primes(n)))
     assert len(primes) == 6

@@ -75,7 +75,7 @@ def test_modp_entries_reduced(P, ctx, O):
     assert P.perm_modp(ctx, A, p) == O.native.ryser_modp(A % p, p)
 
 
-def test_config1_haar_unitary_14(P, ctx, O):
+def test_single_haar_unitary_14(P, ctx, O):
     """Single 14x14 complex128 Haar unitary (QR of CN(0,1) Ginibre, phases folded)."""
     U = E.haar_unitary(14, E.rng(1, 0))
     got = P.perm_c128(ctx, U)

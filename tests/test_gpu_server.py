@@ -167,7 +167,7 @@ def test_unknown_ticket(P, ctx):
         srv.close()
 
 
-def test_config5_stream_matches_batch(P, ctx):
+def test_serving_stream_530_matches_batch(P, ctx):
     """All 530 geodesic and Schur requests of the serving workload, submitted
     at once and as a paced stream: every result equals perm_batch's."""
     import bench
