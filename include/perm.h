@@ -220,7 +220,9 @@ int perm_tune_set(perm_ctx *ctx, int field, int n, const perm_tune *t);
 
 /* Measure candidate chunk lengths for `field` at orders n_lo..n_hi on the
  * context's device (batches of `batch` random matrices per order, or one
- * matrix when batch <= 1) and store the fastest in the table. */
+ * matrix when batch <= 1) and store the fastest in the table.  Jobs below
+ * 2^28 Glynn terms try every length from 3 up and keep the best of five
+ * timings; larger ones try the default +-4, timed once. */
 int perm_autotune(perm_ctx *ctx, int field, int n_lo, int n_hi, int batch);
 
 /* Save / load the table as text lines "field n log2_chunk grid_per_cu",
