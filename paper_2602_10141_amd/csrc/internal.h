@@ -78,6 +78,14 @@ struct perm_ctx {
     // would otherwise fault in fresh pages on every call)
     std::vector<permi::MatIn> scratch_in;
     permi::Plan scratch_plan;
+    // The last small plan built in scratch_plan, with the chunk length it
+    // used per (variant, n): a call with the same inputs and chunk lengths
+    // reuses it, and its upload when plan_buf still holds it.
+    std::vector<permi::MatIn> plan_in;
+    std::vector<std::pair<std::pair<int, int>, int>> plan_chunks;
+    bool plan_cached = false;
+    uint64_t plan_id = 0, uploaded_plan_id = ~0ull;
+    const void *uploaded_ptr = nullptr;
 };
 
 namespace permi {

@@ -18,6 +18,15 @@ enum { hipStreamNonBlocking = 1, hipEventDisableTiming = 2, hipHostMallocDefault
 enum hipMemcpyKind { hipMemcpyHostToDevice, hipMemcpyDeviceToHost, hipMemcpyDeviceToDevice };
 
 hipError_t hipSetDevice(int);
+struct hipDeviceProp_t {
+    int multiProcessorCount;
+    char gcnArchName[256];
+    size_t totalGlobalMem;
+};
+hipError_t hipGetDeviceCount(int *);
+hipError_t hipGetDeviceProperties(hipDeviceProp_t *, int);
+hipError_t hipMemcpy(void *, const void *, size_t, hipMemcpyKind);
+hipError_t hipDeviceSynchronize();
 hipError_t hipStreamCreateWithFlags(hipStream_t *, unsigned);
 hipError_t hipStreamSynchronize(hipStream_t);
 hipError_t hipStreamDestroy(hipStream_t);

@@ -1,0 +1,157 @@
+// Host checks of the planner (csrc/perm.cpp): for seeded random mixes of
+// fields, orders and Gray ranges, every matrix's wave items tile its range
+// exactly once with aligned power-of-two chunks and one partial slot each,
+// launch groups are homogeneous (or fused) and sorted largest first, staged
+// matrices do not overlap, and a repeated call reuses its plan only while
+// the tuning table leaves its chunk lengths unchanged.  Exit code 0 = pass.
+#include <hip/hip_runtime.h>
+
+#include <algorithm>
+#include <cstdio>
+#include <cstdlib>
+#include <random>
+#include <vector>
+
+#include "internal.h"
+#include "kernels.h"
+
+using namespace permk;
+using namespace permi;
+
+static int failures = 0;
+#define CHECK(cond, ...)                                   \
+    do {                                                   \
+        if (!(cond)) {                                     \
+            if (failures++ < 10) {                         \
+                fprintf(stderr, "check failed: %s: ", #cond); \
+                fprintf(stderr, __VA_ARGS__);              \
+                fprintf(stderr, "\n");                     \
+            }                                              \
+        }                                                  \
+    } while (0)
+
+static void check_plan(const perm_ctx *ctx, const std::vector<MatIn> &in, const Plan &pl)
+{
+    CHECK(pl.mats.size() == in.size(), "mats %zu", pl.mats.size());
+    // stage regions: 256-aligned, disjoint, in input order
+    size_t next_stage = 0;
+    for (size_t m = 0; m < in.size(); ++m) {
+        const MatDesc &d = pl.mats[m];
+        CHECK(d.n == in[m].n && d.variant == in[m].variant && d.out_slot == in[m].out_slot, "desc %zu", m);
+        CHECK(d.stage_off % 256 == 0 && d.stage_off >= next_stage, "stage %zu", m);
+        if (in[m].n > 0) next_stage = d.stage_off + stage_bytes(d.variant, d.n);
+    }
+    // items per matrix tile the range once, slots once each
+    std::vector<std::vector<const WaveItem *>> per(in.size());
+    for (const WaveItem &w : pl.items) {
+        CHECK(w.mat < in.size(), "item names matrix %u", w.mat);
+        if (w.mat < in.size()) per[w.mat].push_back(&w);
+    }
+    size_t parts = 0;
+    for (size_t m = 0; m < in.size(); ++m) {
+        const MatIn &a = in[m];
+        const MatDesc &d = pl.mats[m];
+        if (a.n == 0) {
+            CHECK(per[m].empty(), "n = 0 matrix %zu has items", m);
+            continue;
+        }
+        const uint64_t T = 1ull << (a.n - 1);
+        const uint64_t x0 = a.full ? 0 : a.x0, x1 = a.full ? T : a.x1;
+        auto v = per[m];
+        std::sort(v.begin(), v.end(), [](const WaveItem *p, const WaveItem *q) { return p->x0 < q->x0; });
+        uint64_t at = x0;
+        std::vector<bool> slot_seen(d.num_parts, false);
+        for (const WaveItem *w : v) {
+            CHECK(w->x0 == at, "matrix %zu: gap or overlap at %llu", m, (unsigned long long)at);
+            CHECK(w->nlanes >= 1 && w->nlanes <= 64, "lanes");
+            CHECK((w->x0 & ((1ull << w->log2L) - 1)) == 0, "unaligned chunk");
+            CHECK(w->nlanes == 64 || w->log2L == 0, "partial wave with long chunks");
+            if ((a.variant == V_MODP || a.variant == V_MONT)) CHECK(w->log2L <= 20, "F_p chunk");
+            const uint32_t s = w->slot - d.first_part;
+            CHECK(w->slot >= d.first_part && s < d.num_parts && !slot_seen[s], "slot");
+            if (s < d.num_parts) slot_seen[s] = true;
+            at += (uint64_t)w->nlanes << w->log2L;
+        }
+        CHECK(at == x1, "matrix %zu: tiles end at %llu, range ends at %llu", m, (unsigned long long)at,
+              (unsigned long long)x1);
+        CHECK(v.size() == d.num_parts, "parts");
+        parts += d.num_parts;
+    }
+    CHECK(parts == pl.nparts, "nparts");
+    // groups: contiguous, homogeneous unless fused, largest first
+    size_t covered = 0;
+    for (const Group &g : pl.groups) {
+        CHECK(g.first_item == covered, "group order");
+        covered += g.count;
+        uint64_t prev = ~0ull;
+        for (uint32_t q = 0; q < g.count; ++q) {
+            const WaveItem &w = pl.items[g.first_item + q];
+            const MatIn &a = in[w.mat];
+            if (!g.fused) CHECK(a.variant == g.variant && a.n == g.n, "mixed group");
+            else CHECK(a.variant != V_MONT && a.n <= g.nmax_fused, "fused bucket");
+            const uint64_t work = ((uint64_t)w.nlanes << w.log2L) * (uint64_t)a.n;
+            CHECK(work <= prev, "group not sorted largest first");
+            prev = work;
+        }
+    }
+    CHECK(covered == pl.items.size(), "groups cover items");
+    (void)ctx;
+}
+
+int main()
+{
+    perm_ctx *ctx = nullptr;
+    if (perm_ctx_create(0, 0, &ctx) != PERM_OK) return 2;
+    std::mt19937_64 g(2602);
+    for (int trial = 0; trial < 300; ++trial) {
+        const int count = 1 + (int)(g() % (trial % 3 == 0 ? 200 : 12));
+        const bool one_shape = trial % 4 == 0;
+        std::vector<MatIn> in(count);
+        const int v0 = (int)(g() % 3), n0 = (int)(g() % 30);
+        for (int m = 0; m < count; ++m) {
+            MatIn &a = in[m];
+            a.variant = one_shape ? v0 : (int)(g() % 4);
+            a.n = one_shape ? n0 : (int)(g() % 35);
+            a.p = (a.variant >= V_MODP) ? 2147483647u : 0;
+            a.src_off = (uint64_t)m * 16 * 48 * 48;
+            a.out_slot = (uint32_t)m;
+            a.kahan = true;
+            a.full = (g() % 3) != 0 || a.n == 0;
+            if (!a.full) {
+                const uint64_t T = 1ull << (a.n - 1);
+                uint64_t u = g() % (T + 1), w = g() % (T + 1);
+                a.x0 = std::min(u, w);
+                a.x1 = std::max(u, w);
+                a.no_scale = true;
+            }
+        }
+        Plan &pl = ctx->scratch_plan;
+        if (plan(ctx, in, pl) != PERM_OK) { fprintf(stderr, "plan failed\n"); return 1; }
+        check_plan(ctx, in, pl);
+    }
+    // cache: identical small inputs reuse the plan; a table change does not
+    std::vector<MatIn> in(3);
+    for (int m = 0; m < 3; ++m) {
+        in[m].variant = V_MODP; in[m].n = 28; in[m].p = 1073742209u;
+        in[m].src_off = (uint64_t)m * 28 * 28 * 4; in[m].out_slot = (uint32_t)m;
+    }
+    Plan &pl = ctx->scratch_plan;
+    plan(ctx, in, pl);
+    const uint64_t id = ctx->plan_id;
+    const size_t items = pl.items.size();
+    plan(ctx, in, pl);
+    CHECK(ctx->plan_id == id, "identical call rebuilt the plan");
+    perm_tune t{12, 0};
+    perm_tune_set(ctx, PERM_MODP, 28, &t);
+    plan(ctx, in, pl);
+    CHECK(ctx->plan_id != id, "table change did not rebuild");
+    CHECK(pl.items.size() * 4 == items, "chunk 2^12 should give a quarter of the items of 2^10");
+    check_plan(ctx, in, pl);
+    in[1].src_off += 4;
+    plan(ctx, in, pl);
+    CHECK(ctx->plan_id != id, "changed input reused the plan");
+    perm_ctx_destroy(ctx);
+    printf("planner checks: %d failures\n", failures);
+    fflush(stdout);
+    _Exit(failures ? 1 : 0);
+}

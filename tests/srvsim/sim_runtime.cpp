@@ -115,6 +115,34 @@ void sim_enqueue(hipStream_t s, std::function<void()> fn)
 }
 
 hipError_t hipSetDevice(int) { return hipSuccess; }
+hipError_t hipGetDeviceCount(int *n)
+{
+    *n = 1;
+    return hipSuccess;
+}
+hipError_t hipGetDeviceProperties(hipDeviceProp_t *p, int)
+{
+    p->multiProcessorCount = 256;
+    strcpy(p->gcnArchName, "simulated");
+    p->totalGlobalMem = (size_t)1 << 36;
+    return hipSuccess;
+}
+hipError_t hipMemcpy(void *d, const void *src, size_t n, hipMemcpyKind)
+{
+    drain(nullptr);
+    memcpy(d, src, n);
+    return hipSuccess;
+}
+hipError_t hipDeviceSynchronize()
+{
+    std::vector<SimStream *> all;
+    {
+        std::lock_guard<std::mutex> lk(mu);
+        all = streams;
+    }
+    for (SimStream *s : all) drain(s == null_stream ? nullptr : s);
+    return hipSuccess;
+}
 hipError_t hipStreamCreateWithFlags(hipStream_t *s, unsigned)
 {
     std::lock_guard<std::mutex> lk(mu);

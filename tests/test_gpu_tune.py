@@ -82,3 +82,31 @@ def test_autotune_and_roundtrip(P, oracle_lib, tmp_path):
             P.perm_tune_set(ctx2, "modp", 30, 22)        # F_p chunks limited to 2^20
     finally:
         ctx2.close()
+
+
+def test_repeated_calls_follow_the_table(P):
+    """A repeated call reuses its plan only while the chunk lengths it used
+    are unchanged: after a table change the next call takes the new
+    partition (bit-identical to a fresh context with that table)."""
+    A = E.ginibre_complex(17, E.rng(35, 0))
+    B = E.ginibre_complex(17, E.rng(35, 1))
+    ctx, fresh = P.Context(0), P.Context(0)
+    try:
+        a0 = P.perm_c128(ctx, A)
+        b0 = P.perm_c128(ctx, B)                 # same plan, new data
+        assert P.perm_c128(fresh, B) == b0
+        for c in (3, 6, 0):
+            P.perm_tune_set(ctx, "c128", 17, c)
+            P.perm_tune_set(fresh, "c128", 17, c)
+            got = P.perm_c128(ctx, A)
+            other = P.Context(0)
+            try:
+                P.perm_tune_set(other, "c128", 17, c)
+                assert got == P.perm_c128(other, A)
+            finally:
+                other.close()
+            if c == 0:
+                assert got == a0
+    finally:
+        ctx.close()
+        fresh.close()
