@@ -68,7 +68,7 @@ struct perm_ctx {
     size_t pinned_cap = 0;
     hipEvent_t pinned_ev = nullptr;
     bool pinned_busy = false;
-    uint64_t ctr_value = 0;
+    permk::CtrState ctr_state;
     int grid_per_cu = 0;
     std::map<std::pair<int, int>, perm_tune> tune;
     std::map<int, int> occ;

@@ -82,15 +82,33 @@ int launch_stage(const MatDesc *d_mats, int nmats, const void *src, void *stage,
 
 // Walk: `count` wave items, all of one (variant, n) when `fused` is false;
 // with fused = true the matrices may mix variants and orders n <= nmax_fused.
-// `ctr` is a 64-bit device counter whose value at launch time is `base`; the
-// launch adds exactly count + (waves launched) to it, which is returned in
-// *ctr_advance.
+// `ctr` points at CTR_BYTES of device counters (see below).
+//
+// Work counters of the persistent kernels: one per XCD (MI355X has 8), 256
+// bytes apart.  Block b takes runs of items from counter b mod `groups`
+// (groups = min(8, grid)); workgroups are dispatched round-robin over the
+// XCDs, so each counter's atomics stay in one XCD's L2.  Counter x serves the
+// runs r = x, x + groups, x + 2 groups, ... (striding keeps the largest-first
+// order balanced across XCDs).  The host tracks each counter's value.
+constexpr int CTR_GROUPS = 8;
+constexpr int CTR_STRIDE = 32;                                  // in uint64
+constexpr size_t CTR_BYTES = (size_t)CTR_GROUPS * CTR_STRIDE * 8;
+struct CtrState {
+    uint64_t base[CTR_GROUPS] = {};
+};
+struct CtrArgs {                 // kernel argument (by value)
+    uint64_t base[CTR_GROUPS];
+    uint32_t groups;
+    uint32_t pad;
+};
+
 // Waves claim `grab` consecutive items per atomic (grab >= 1): tiny items
-// would otherwise serialize on the one counter.
+// would otherwise make the claims the bottleneck.  `state` holds the
+// counters' values before the launch and is advanced past it.
 int launch_walk(int variant, int n, bool kahan, bool fused, int nmax_fused,
                 const WaveItem *d_items, uint32_t count, uint32_t grab, const MatDesc *d_mats,
                 const void *stage, double *partials, unsigned long long *ctr,
-                uint64_t base, int grid_blocks, void *stream, uint64_t *ctr_advance);
+                CtrState *state, int grid_blocks, void *stream);
 
 // Items per atomic claim for items of at most 2^max_log2L steps per lane:
 // enough that one claim is at least 64 lane-steps of walk, at most 16.

@@ -460,7 +460,6 @@ int execute(perm_ctx *ctx, Plan &pl, const void *src, void *out, size_t out_slot
         const uint32_t runs = (g.count + grab - 1) / grab;
         const int blocks_needed = (int)((runs + (BLOCK / WAVE) - 1) / (BLOCK / WAVE));
         const int grid = std::max(1, std::min(blocks_needed, per_cu * ctx->num_cus));
-        uint64_t adv = 0;
         std::pair<hipEvent_t, hipEvent_t> ev{nullptr, nullptr};
         if (ctx->prof_on) {
             if (ctx->prof_pool.empty()) {
@@ -475,9 +474,8 @@ int execute(perm_ctx *ctx, Plan &pl, const void *src, void *out, size_t out_slot
         HIPCHK((hipError_t)launch_walk(g.variant, g.n, g.kahan, g.fused, g.nmax_fused,
                                        d_items + g.first_item, g.count, grab, d_mats, ctx->stage.p,
                                        (double *)ctx->partials.p,
-                                       (unsigned long long *)ctx->ctr.p, ctx->ctr_value, grid, s,
-                                       &adv));
-        ctx->ctr_value += adv;
+                                       (unsigned long long *)ctx->ctr.p, &ctx->ctr_state, grid,
+                                       s));
         if (ctx->prof_on) {
             HIPCHK(hipEventRecord(ev.second, s));
             ctx->prof_pending.push_back(ev);
@@ -518,15 +516,15 @@ extern "C" int perm_ctx_create(int device, size_t hbm_budget, perm_ctx **out)
         delete c;
         return fail(PERM_EDEVICE, "stream/event creation failed");
     }
-    int rc = ensure(c, c->ctr, 256);
+    int rc = ensure(c, c->ctr, CTR_BYTES);
     if (rc != PERM_OK) { perm_ctx_destroy(c); return rc; }
     // kernels run on non-blocking streams, which do not order after the null
     // stream: the counter is zero before the first launch by waiting here
-    if (hipMemset(c->ctr.p, 0, 256) != hipSuccess || hipStreamSynchronize(nullptr) != hipSuccess) {
+    if (hipMemset(c->ctr.p, 0, CTR_BYTES) != hipSuccess || hipStreamSynchronize(nullptr) != hipSuccess) {
         perm_ctx_destroy(c);
         return fail(PERM_EDEVICE, "counter init failed");
     }
-    c->ctr_value = 0;
+    c->ctr_state = CtrState{};
     *out = c;
     return PERM_OK;
 }

@@ -157,8 +157,8 @@ struct perm_srv {
     Arena arena;
     void *table_dev = nullptr;           // max_inflight MatDescs
     void *results_dev = nullptr;         // max_inflight * 16 bytes
-    void *ctr_dev = nullptr;             // one 64-bit counter per stream (256 B apart)
-    uint64_t ctr_value[2] = {0, 0};
+    void *ctr_dev = nullptr;             // one block of work counters per stream
+    CtrState ctr_state[2];
     hipStream_t streams[2] = {nullptr, nullptr};
     bool prev_done_valid = false;        // slices[cur ^ 1].done refers to the previous slice
     std::vector<int> free_slots;
@@ -319,14 +319,12 @@ int launch_items(perm_srv *S, const std::vector<WaveItem> &items,
         grab = std::max(1u, std::min(grab, count / (2u * (uint32_t)(occ * S->ctx->num_cus * 4))));
         const uint32_t runs = (count + grab - 1) / grab;
         const int grid = std::max(1, std::min((int)((runs + 3) / 4), occ * S->ctx->num_cus));
-        uint64_t adv = 0;
-        unsigned long long *ctr = (unsigned long long *)((char *)S->ctr_dev + 256 * S->cur);
+        unsigned long long *ctr = (unsigned long long *)((char *)S->ctr_dev + CTR_BYTES * S->cur);
         SRV_HIP((hipError_t)launch_walk(item_variant[i], item_n[i], kahan, fz,
                                         nmax <= FUSED_BUCKETS[0] ? FUSED_BUCKETS[0] : FUSED_BUCKETS[1],
                                         d_items_base + i, count, grab, (const MatDesc *)S->table_dev,
                                         S->arena_dev, (double *)S->arena_dev, ctr,
-                                        S->ctr_value[S->cur], grid, s, &adv));
-        S->ctr_value[S->cur] += adv;
+                                        &S->ctr_state[S->cur], grid, s));
         i = j;
     }
     return PERM_OK;
@@ -706,9 +704,9 @@ extern "C" int perm_srv_create(perm_ctx *ctx, const perm_srv_cfg *cfg, perm_srv 
     const size_t scratch = res_b * 2 + 2 * (2 * align256(sizeof(MatDesc) * mi) +
                                             align256(sizeof(WaveItem) * kSliceItems));
     if (hipMalloc(&S->results_dev, scratch) != hipSuccess) return bail("results");
-    if (hipMalloc(&S->ctr_dev, 512) != hipSuccess) return bail("counter");
+    if (hipMalloc(&S->ctr_dev, 2 * CTR_BYTES) != hipSuccess) return bail("counter");
     // zeroed before the worker's first launch on the non-blocking streams
-    if (hipMemset(S->ctr_dev, 0, 512) != hipSuccess || hipStreamSynchronize(nullptr) != hipSuccess)
+    if (hipMemset(S->ctr_dev, 0, 2 * CTR_BYTES) != hipSuccess || hipStreamSynchronize(nullptr) != hipSuccess)
         return bail("counter init");
     for (Slice &sl : S->slices) {
         if (hipEventCreate(&sl.done) != hipSuccess ||

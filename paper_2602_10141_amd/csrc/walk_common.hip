@@ -188,21 +188,30 @@ int walk_occupancy(int variant, int n, bool kahan, bool fused, int nmax_fused, i
 
 int launch_walk(int variant, int n, bool kahan, bool fused, int nmax_fused, const WaveItem *d_items,
                 uint32_t count, uint32_t grab, const MatDesc *d_mats, const void *stage,
-                double *partials, unsigned long long *ctr, uint64_t base, int grid_blocks,
-                void *stream, uint64_t *ctr_advance)
+                double *partials, unsigned long long *ctr, CtrState *state, int grid_blocks,
+                void *stream)
 {
     WalkFn f = pick(variant, n, kahan, fused, nmax_fused);
-    if (!f || grab < 1) return (int)hipErrorInvalidValue;
+    if (!f || grab < 1 || !state) return (int)hipErrorInvalidValue;
     if (grid_blocks < 1) grid_blocks = 1;
+    CtrArgs ca{};
+    ca.groups = (uint32_t)(grid_blocks < CTR_GROUPS ? grid_blocks : CTR_GROUPS);
+    for (int x = 0; x < CTR_GROUPS; ++x) ca.base[x] = state->base[x];
     const char *st = (const char *)stage;
     void *args[] = {(void *)&d_items, (void *)&count, (void *)&grab, (void *)&d_mats, (void *)&st,
-                    (void *)&partials, (void *)&ctr, (void *)&base};
+                    (void *)&partials, (void *)&ctr, (void *)&ca};
     hipError_t e = hipLaunchKernel((const void *)f, dim3(grid_blocks), dim3(BLOCK), args, 0,
                                    (hipStream_t)stream);
     if (e != hipSuccess) return (int)e;
-    // one claim per run of `grab` items, plus the one failing claim per wave
+    // Counter x: one claim per run r = x (mod groups), plus the one failing
+    // claim of every wave of the blocks b = x (mod groups).
     const uint64_t runs = ((uint64_t)count + grab - 1) / grab;
-    *ctr_advance = runs + (uint64_t)grid_blocks * (BLOCK / WAVE);
+    const uint64_t g = ca.groups;
+    for (uint64_t x = 0; x < g; ++x) {
+        const uint64_t runs_x = runs > x ? (runs - x + g - 1) / g : 0;
+        const uint64_t blocks_x = ((uint64_t)grid_blocks - x + g - 1) / g;
+        state->base[x] += runs_x + blocks_x * (BLOCK / WAVE);
+    }
     return (int)hipGetLastError();
 }
 

@@ -600,19 +600,31 @@ struct Occupancy {
 // (largest first, as ordered by the host) until the counter passes the
 // number of runs.  W > 0 overrides the waves-per-SIMD target (used when
 // tuning the budgets).
+// Next run of items for this block's counter group, or `runs` (= none left).
+__device__ __forceinline__ uint64_t next_run(unsigned long long *c, uint64_t base, int lane,
+                                             uint32_t x, uint32_t groups, uint32_t runs)
+{
+    const uint64_t r = x + (uint64_t)groups * next_item(c, base, lane);
+    return r < runs ? r : runs;
+}
+
 template <int V, int N, bool KAHAN, int W = 0>
 __global__ __launch_bounds__(BLOCK)
 __attribute__((amdgpu_waves_per_eu(W > 0 ? W : Occupancy<V, N>::waves, 8)))
 void walk_kernel(const WaveItem *items, uint32_t count, uint32_t grab,
                                                      const MatDesc *mats, const char *stage,
                                                      double *partials, unsigned long long *ctr,
-                                                     uint64_t base)
+                                                     CtrArgs ca)
 {
     const int lane = threadIdx.x & (WAVE - 1);
     const uint32_t runs = (uint32_t)(((uint64_t)count + grab - 1) / grab);
-    for (uint32_t r = next_item(ctr, base, lane); r < runs; r = next_item(ctr, base, lane)) {
-        const uint32_t end = (uint32_t)min((uint64_t)count, (uint64_t)(r + 1) * grab);
-        for (uint32_t idx = r * grab; idx < end; ++idx) {
+    const uint32_t x = blockIdx.x % ca.groups;
+    unsigned long long *c = ctr + CTR_STRIDE * x;
+    const uint64_t base = ca.base[x];
+    for (uint64_t r = next_run(c, base, lane, x, ca.groups, runs); r < runs;
+         r = next_run(c, base, lane, x, ca.groups, runs)) {
+        const uint32_t end = (uint32_t)min((uint64_t)count, (r + 1) * grab);
+        for (uint32_t idx = (uint32_t)(r * grab); idx < end; ++idx) {
             const WaveItem it = sload(items + idx);
             const MatDesc md = sload(mats + it.mat);
             run_item<typename OpsFor<V, N, KAHAN>::type>(it, md, stage, partials, lane);
@@ -645,13 +657,17 @@ __attribute__((amdgpu_waves_per_eu(Occupancy<V_C128, NF>::waves, 8)))
 void walk_fused(const WaveItem *items, uint32_t count, uint32_t grab,
                                                     const MatDesc *mats, const char *stage,
                                                     double *partials, unsigned long long *ctr,
-                                                    uint64_t base)
+                                                    CtrArgs ca)
 {
     const int lane = threadIdx.x & (WAVE - 1);
     const uint32_t runs = (uint32_t)(((uint64_t)count + grab - 1) / grab);
-    for (uint32_t r = next_item(ctr, base, lane); r < runs; r = next_item(ctr, base, lane)) {
-        const uint32_t end = (uint32_t)min((uint64_t)count, (uint64_t)(r + 1) * grab);
-        for (uint32_t idx = r * grab; idx < end; ++idx) {
+    const uint32_t x = blockIdx.x % ca.groups;
+    unsigned long long *c = ctr + CTR_STRIDE * x;
+    const uint64_t base = ca.base[x];
+    for (uint64_t r = next_run(c, base, lane, x, ca.groups, runs); r < runs;
+         r = next_run(c, base, lane, x, ca.groups, runs)) {
+        const uint32_t end = (uint32_t)min((uint64_t)count, (r + 1) * grab);
+        for (uint32_t idx = (uint32_t)(r * grab); idx < end; ++idx) {
             const WaveItem it = sload(items + idx);
             const MatDesc md = sload(mats + it.mat);
             run_fused<KAHAN>(std::make_integer_sequence<int, NF>{}, md.n, md.variant, it, md,
@@ -662,7 +678,7 @@ void walk_fused(const WaveItem *items, uint32_t count, uint32_t grab,
 
 // ------------------------------------------------ instantiation tables
 using WalkFn = void (*)(const WaveItem *, uint32_t, uint32_t, const MatDesc *, const char *,
-                        double *, unsigned long long *, uint64_t);
+                        double *, unsigned long long *, CtrArgs);
 
 template <int V, bool K, int LO, int... Ns>
 inline WalkFn walk_fn_range(int n, std::integer_sequence<int, Ns...>)

@@ -5,11 +5,10 @@
 
 namespace permk {
 int launch_stage(const MatDesc *, int, const void *, void *, void *) { return 0; }
-int launch_walk(int, int, bool, bool, int, const WaveItem *, uint32_t count, uint32_t grab,
-                const MatDesc *, const void *, double *, unsigned long long *, uint64_t, int grid,
-                void *, uint64_t *adv)
+int launch_walk(int, int, bool, bool, int, const WaveItem *, uint32_t, uint32_t,
+                const MatDesc *, const void *, double *, unsigned long long *, CtrState *, int,
+                void *)
 {
-    *adv = (count + grab - 1) / grab + (uint64_t)grid * 4;
     return 0;
 }
 int walk_occupancy(int, int, bool, bool, int, int *b)

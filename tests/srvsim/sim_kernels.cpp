@@ -58,34 +58,44 @@ int launch_stage(const MatDesc *d_mats, int nmats, const void *src, void *stage,
 
 int launch_walk(int, int, bool, bool, int, const WaveItem *d_items, uint32_t count,
                 uint32_t grab, const MatDesc *d_mats, const void *stage, double *partials,
-                unsigned long long *ctr, uint64_t base, int grid_blocks, void *stream,
-                uint64_t *ctr_advance)
+                unsigned long long *ctr, CtrState *state, int grid_blocks, void *stream)
 {
-    if (grab < 1) return 1;
+    if (grab < 1 || !state) return 1;
+    if (grid_blocks < 1) grid_blocks = 1;
     const uint64_t runs = ((uint64_t)count + grab - 1) / grab;
-    *ctr_advance = runs + (uint64_t)grid_blocks * (BLOCK / WAVE);
+    const uint32_t groups = (uint32_t)std::min(grid_blocks, CTR_GROUPS);
+    CtrState before = *state;
+    for (uint32_t x = 0; x < groups; ++x) {
+        const uint64_t runs_x = runs > x ? (runs - x + groups - 1) / groups : 0;
+        const uint64_t blocks_x = ((uint64_t)grid_blocks - x + groups - 1) / groups;
+        state->base[x] += runs_x + blocks_x * (BLOCK / WAVE);
+    }
     sim_enqueue((hipStream_t)stream, [=] {
-        uint64_t v = *ctr;
-        if (v != base) sim_desync++;
-        long waves = (long)grid_blocks * (BLOCK / WAVE);
-        while (waves > 0) {
-            const uint32_t r = (uint32_t)(v - base);
-            ++v;
-            if (r >= runs) {
-                --waves;
-                continue;
+        for (uint32_t x = 0; x < groups; ++x) {
+            unsigned long long *c = ctr + CTR_STRIDE * x;
+            const uint64_t base = before.base[x];
+            uint64_t v = *c;
+            if (v != base) sim_desync++;
+            long waves = (long)(((uint64_t)grid_blocks - x + groups - 1) / groups) * (BLOCK / WAVE);
+            while (waves > 0) {
+                const uint64_t r = x + (uint64_t)groups * (uint32_t)(v - base);
+                ++v;
+                if (r >= runs) {
+                    --waves;
+                    continue;
+                }
+                const uint64_t end = std::min<uint64_t>(count, (r + 1) * grab);
+                for (uint64_t idx = r * grab; idx < end; ++idx) {
+                    const WaveItem &w = d_items[idx];
+                    const MatDesc &d = d_mats[w.mat];
+                    uint64_t *slot = (uint64_t *)((char *)partials + 16 * (size_t)w.slot);
+                    slot[0] = *(const uint64_t *)((const char *)stage + d.stage_off);
+                    slot[1] = w.x0;
+                    sim_items++;
+                }
             }
-            const uint64_t end = std::min<uint64_t>(count, (uint64_t)(r + 1) * grab);
-            for (uint64_t idx = (uint64_t)r * grab; idx < end; ++idx) {
-                const WaveItem &w = d_items[idx];
-                const MatDesc &d = d_mats[w.mat];
-                uint64_t *slot = (uint64_t *)((char *)partials + 16 * (size_t)w.slot);
-                slot[0] = *(const uint64_t *)((const char *)stage + d.stage_off);
-                slot[1] = w.x0;
-                sim_items++;
-            }
+            *c = v;
         }
-        *ctr = v;
         if (ns_per_item() > 0)
             std::this_thread::sleep_for(std::chrono::nanoseconds((long)(ns_per_item() * count)));
     });
