@@ -86,9 +86,10 @@ int launch_stage(const MatDesc *d_mats, int nmats, const void *src, void *stage,
 //
 // Work counters of the persistent kernels: one per XCD (MI355X has 8), 256
 // bytes apart.  Block b takes runs of items from counter b mod `groups`
-// (groups = min(8, grid)); workgroups are dispatched round-robin over the
-// XCDs, so each counter's atomics stay in one XCD's L2.  Counter x serves the
-// runs r = x, x + groups, x + 2 groups, ... (striding keeps the largest-first
+// (groups = the largest power of two <= min(8, grid), so that the remainder
+// is a scalar AND); workgroups are dispatched round-robin over the XCDs, so
+// each counter serves the blocks of one XCD.  Counter x serves the runs
+// r = x, x + groups, x + 2 groups, ... (striding keeps the largest-first
 // order balanced across XCDs).  The host tracks each counter's value.
 constexpr int CTR_GROUPS = 8;
 constexpr int CTR_STRIDE = 32;                                  // in uint64
@@ -96,10 +97,16 @@ constexpr size_t CTR_BYTES = (size_t)CTR_GROUPS * CTR_STRIDE * 8;
 struct CtrState {
     uint64_t base[CTR_GROUPS] = {};
 };
+inline uint32_t ctr_groups(int grid_blocks)
+{
+    uint32_t g = 1;
+    while (g < (uint32_t)CTR_GROUPS && (int)(2 * g) <= grid_blocks) g *= 2;
+    return g;
+}
 struct CtrArgs {                 // kernel argument (by value)
     uint64_t base[CTR_GROUPS];
     uint32_t groups;
-    uint32_t pad;
+    uint32_t runs;               // ceil(count / grab), computed on the host
 };
 
 // Waves claim `grab` consecutive items per atomic (grab >= 1): tiny items

@@ -194,8 +194,10 @@ int launch_walk(int variant, int n, bool kahan, bool fused, int nmax_fused, cons
     WalkFn f = pick(variant, n, kahan, fused, nmax_fused);
     if (!f || grab < 1 || !state) return (int)hipErrorInvalidValue;
     if (grid_blocks < 1) grid_blocks = 1;
+    const uint64_t runs = ((uint64_t)count + grab - 1) / grab;
     CtrArgs ca{};
-    ca.groups = (uint32_t)(grid_blocks < CTR_GROUPS ? grid_blocks : CTR_GROUPS);
+    ca.groups = ctr_groups(grid_blocks);
+    ca.runs = (uint32_t)runs;
     for (int x = 0; x < CTR_GROUPS; ++x) ca.base[x] = state->base[x];
     const char *st = (const char *)stage;
     void *args[] = {(void *)&d_items, (void *)&count, (void *)&grab, (void *)&d_mats, (void *)&st,
@@ -205,7 +207,6 @@ int launch_walk(int variant, int n, bool kahan, bool fused, int nmax_fused, cons
     if (e != hipSuccess) return (int)e;
     // Counter x: one claim per run r = x (mod groups), plus the one failing
     // claim of every wave of the blocks b = x (mod groups).
-    const uint64_t runs = ((uint64_t)count + grab - 1) / grab;
     const uint64_t g = ca.groups;
     for (uint64_t x = 0; x < g; ++x) {
         const uint64_t runs_x = runs > x ? (runs - x + g - 1) / g : 0;

@@ -617,8 +617,11 @@ void walk_kernel(const WaveItem *items, uint32_t count, uint32_t grab,
                                                      CtrArgs ca)
 {
     const int lane = threadIdx.x & (WAVE - 1);
-    const uint32_t runs = (uint32_t)(((uint64_t)count + grab - 1) / grab);
-    const uint32_t x = blockIdx.x % ca.groups;
+    // Scalar operations only, so that the counter address and the loop bound
+    // stay in SGPRs (a divide would run on the VALU and hold them in VGPRs,
+    // which the walk needs for its row sums).
+    const uint32_t runs = ca.runs;
+    const uint32_t x = blockIdx.x & (ca.groups - 1);
     unsigned long long *c = ctr + CTR_STRIDE * x;
     const uint64_t base = ca.base[x];
     for (uint64_t r = next_run(c, base, lane, x, ca.groups, runs); r < runs;
@@ -660,8 +663,11 @@ void walk_fused(const WaveItem *items, uint32_t count, uint32_t grab,
                                                     CtrArgs ca)
 {
     const int lane = threadIdx.x & (WAVE - 1);
-    const uint32_t runs = (uint32_t)(((uint64_t)count + grab - 1) / grab);
-    const uint32_t x = blockIdx.x % ca.groups;
+    // Scalar operations only, so that the counter address and the loop bound
+    // stay in SGPRs (a divide would run on the VALU and hold them in VGPRs,
+    // which the walk needs for its row sums).
+    const uint32_t runs = ca.runs;
+    const uint32_t x = blockIdx.x & (ca.groups - 1);
     unsigned long long *c = ctr + CTR_STRIDE * x;
     const uint64_t base = ca.base[x];
     for (uint64_t r = next_run(c, base, lane, x, ca.groups, runs); r < runs;

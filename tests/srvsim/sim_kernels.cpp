@@ -63,7 +63,7 @@ int launch_walk(int, int, bool, bool, int, const WaveItem *d_items, uint32_t cou
     if (grab < 1 || !state) return 1;
     if (grid_blocks < 1) grid_blocks = 1;
     const uint64_t runs = ((uint64_t)count + grab - 1) / grab;
-    const uint32_t groups = (uint32_t)std::min(grid_blocks, CTR_GROUPS);
+    const uint32_t groups = ctr_groups(grid_blocks);
     CtrState before = *state;
     for (uint32_t x = 0; x < groups; ++x) {
         const uint64_t runs_x = runs > x ? (runs - x + groups - 1) / groups : 0;
