@@ -67,6 +67,22 @@ inline size_t stage_bytes(int variant, int n)
     return 0;
 }
 
+// Approximate VALU instructions of one Gray step (flip, product, signed
+// accumulate) per lane, used to order wave items by duration: a complex step
+// is 2n adds and n - 1 four-instruction complex products, a real step n adds
+// and n - 1 products, an F_p (Barrett) step n adds and n - 1 six-instruction
+// products; Montgomery's 32-bit products issue at a quarter of that rate.
+inline uint64_t step_cost(int variant, int n)
+{
+    switch (variant) {
+    case V_C128: return 6 * (uint64_t)n;
+    case V_F64:  return 2 * (uint64_t)n;
+    case V_MODP: return 7 * (uint64_t)n;
+    case V_MONT: return 10 * (uint64_t)n;
+    }
+    return (uint64_t)n;
+}
+
 // Bytes of one source matrix entry for a variant.
 inline size_t src_entry_bytes(int variant)
 {
@@ -85,7 +101,7 @@ int launch_stage(const MatDesc *d_mats, int nmats, const void *src, void *stage,
 // `ctr` points at CTR_BYTES of device counters (see below).
 //
 // Work counters of the persistent kernels: one per XCD (MI355X has 8), 256
-// bytes apart.  Block b takes runs of items from counter b mod `groups`
+// bytes apart.  Block b claims runs of items from counter b mod `groups`
 // (groups = the largest power of two <= min(8, grid), so that the remainder
 // is a scalar AND); workgroups are dispatched round-robin over the XCDs, so
 // each counter serves the blocks of one XCD.  Counter x serves the runs
@@ -109,9 +125,10 @@ struct CtrArgs {                 // kernel argument (by value)
     uint32_t runs;               // ceil(count / grab), computed on the host
 };
 
-// Waves claim `grab` consecutive items per atomic (grab >= 1): tiny items
-// would otherwise make the claims the bottleneck.  `state` holds the
-// counters' values before the launch and is advanced past it.
+// Blocks claim runs of (BLOCK / WAVE) * grab consecutive items per atomic
+// (grab >= 1), the block's waves taking every (BLOCK / WAVE)-th item of the
+// run: tiny items would otherwise make the claims the bottleneck.  `state`
+// holds the counters' values before the launch and is advanced past it.
 int launch_walk(int variant, int n, bool kahan, bool fused, int nmax_fused,
                 const WaveItem *d_items, uint32_t count, uint32_t grab, const MatDesc *d_mats,
                 const void *stage, double *partials, unsigned long long *ctr,

@@ -129,8 +129,10 @@ int default_log2_chunk(int variant, int n)
     // device (three primes for F_p, 2,000 to 50,000 matrices for floats):
     //  * floats: one item per matrix up to n = 13 (c = n - 7: shorter walks
     //    make the per-lane seed dominate), four items at n = 14, 15 (a
-    //    single permanent's latency), two for n = 16..20 (within 2% of one
-    //    item in batch throughput), c = 12 at n = 21, 22 and 10 beyond;
+    //    single permanent's latency; one item is up to 13% faster in
+    //    batches), two at n = 16, 17, four for n = 18..20 (a block's four
+    //    waves then walk one matrix), c = 11 at n = 21, 22 and 10 beyond
+    //    (enough items for one large matrix to fill the device);
     //  * F_p: c = n/2 - 5 up to n = 26 and n/2 - 4 (at most 13) from n = 28,
     //    so that the per-lane seed (n^2 work) stays near 1% of the walk with
     //    a few items per resident wave and the host plan stays small, then
@@ -143,8 +145,8 @@ int default_log2_chunk(int variant, int n)
     }
     if (n < 14) return std::max(3, n - 7);
     if (n < 16) return n - 9;
-    if (n <= 20) return n - 8;
-    return n <= 22 ? 12 : 10;
+    if (n <= 17) return n - 8;
+    return n <= 22 ? std::min(n - 9, 11) : 10;
 }
 
 int log2_chunk_for(const perm_ctx *ctx, int variant, int n)
@@ -323,10 +325,12 @@ int plan(perm_ctx *ctx, const std::vector<MatIn> &in, Plan &pl)
             d.num_parts = np;
             pl.nparts += np;
         }
-        // largest first (stable): key = indices per item x n
+        // longest first (stable): key = indices per item x cost of a step, so
+        // that the waves of a block, which take neighbouring items, finish
+        // together in a fused launch of mixed fields
         const size_t cnt = gi.size() - g0;
         auto work = [&](const WaveItem &w) {
-            return ((uint64_t)w.nlanes << w.log2L) * (uint64_t)in[w.mat].n;
+            return ((uint64_t)w.nlanes << w.log2L) * step_cost(in[w.mat].variant, in[w.mat].n);
         };
         bool uniform = true;
         for (size_t q = 1; q < cnt && uniform; ++q) uniform = work(gi[g0 + q]) == work(gi[g0]);

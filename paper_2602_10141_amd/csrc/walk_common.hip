@@ -194,7 +194,8 @@ int launch_walk(int variant, int n, bool kahan, bool fused, int nmax_fused, cons
     WalkFn f = pick(variant, n, kahan, fused, nmax_fused);
     if (!f || grab < 1 || !state) return (int)hipErrorInvalidValue;
     if (grid_blocks < 1) grid_blocks = 1;
-    const uint64_t runs = ((uint64_t)count + grab - 1) / grab;
+    const uint64_t per_run = (uint64_t)(BLOCK / WAVE) * grab;
+    const uint64_t runs = ((uint64_t)count + per_run - 1) / per_run;
     CtrArgs ca{};
     ca.groups = ctr_groups(grid_blocks);
     ca.runs = (uint32_t)runs;
@@ -206,12 +207,12 @@ int launch_walk(int variant, int n, bool kahan, bool fused, int nmax_fused, cons
                                    (hipStream_t)stream);
     if (e != hipSuccess) return (int)e;
     // Counter x: one claim per run r = x (mod groups), plus the one failing
-    // claim of every wave of the blocks b = x (mod groups).
+    // claim of every block b = x (mod groups).
     const uint64_t g = ca.groups;
     for (uint64_t x = 0; x < g; ++x) {
         const uint64_t runs_x = runs > x ? (runs - x + g - 1) / g : 0;
         const uint64_t blocks_x = ((uint64_t)grid_blocks - x + g - 1) / g;
-        state->base[x] += runs_x + blocks_x * (BLOCK / WAVE);
+        state->base[x] += runs_x + blocks_x;
     }
     return (int)hipGetLastError();
 }

@@ -596,18 +596,45 @@ struct Occupancy {
                     : (N > 40 ? 3 : 4);
 };
 
-// Persistent kernel: every wave claims runs of `grab` consecutive wave items
-// (largest first, as ordered by the host) until the counter passes the
-// number of runs.  W > 0 overrides the waves-per-SIMD target (used when
-// tuning the budgets).
 // Next run of items for this block's counter group, or `runs` (= none left).
-__device__ __forceinline__ uint64_t next_run(unsigned long long *c, uint64_t base, int lane,
+__device__ __forceinline__ uint32_t next_run(unsigned long long *c, uint64_t base, int lane,
                                              uint32_t x, uint32_t groups, uint32_t runs)
 {
     const uint64_t r = x + (uint64_t)groups * next_item(c, base, lane);
-    return r < runs ? r : runs;
+    return r < runs ? (uint32_t)r : runs;
 }
 
+// Block-level claims.  Wave 0 of a block claims a run of WPB * grab
+// consecutive wave items and publishes it in LDS; wave w takes the items
+// w, w + WPB, w + 2 WPB, ... of the run.  Consecutive items belong to the
+// same matrix (the host orders them so), so the four waves of a block walk
+// one matrix side by side and its columns are shared in the CU's scalar
+// cache; with one claim per wave, the waves of a CU walked as many different
+// matrices as there were waves and the scalar cache missed on about half of
+// the column loads in batches.  The LDS slot is double-buffered: the slot
+// written for claim i + 2 is read for claim i before every wave passes the
+// barrier of claim i + 1, so one barrier per claim suffices.
+constexpr uint32_t WPB = BLOCK / WAVE;
+
+struct BlockClaims {
+    unsigned long long *c;
+    uint64_t base;
+    uint32_t x, groups, runs, wave, parity;
+    uint32_t *slot;                 // two uint32 in LDS
+
+    __device__ __forceinline__ uint32_t next(int lane)
+    {
+        if (wave == 0) slot[parity] = next_run(c, base, lane, x, groups, runs);
+        __syncthreads();
+        const uint32_t r = __builtin_amdgcn_readfirstlane(slot[parity]);
+        parity ^= 1u;
+        return r;
+    }
+};
+
+// Persistent kernel: blocks claim runs (largest items first, as ordered by
+// the host) until the counter passes the number of runs.  W > 0 overrides
+// the waves-per-SIMD target (used when tuning the budgets).
 template <int V, int N, bool KAHAN, int W = 0>
 __global__ __launch_bounds__(BLOCK)
 __attribute__((amdgpu_waves_per_eu(W > 0 ? W : Occupancy<V, N>::waves, 8)))
@@ -616,18 +643,18 @@ void walk_kernel(const WaveItem *items, uint32_t count, uint32_t grab,
                                                      double *partials, unsigned long long *ctr,
                                                      CtrArgs ca)
 {
+    __shared__ uint32_t slot[2];
     const int lane = threadIdx.x & (WAVE - 1);
     // Scalar operations only, so that the counter address and the loop bound
     // stay in SGPRs (a divide would run on the VALU and hold them in VGPRs,
     // which the walk needs for its row sums).
-    const uint32_t runs = ca.runs;
     const uint32_t x = blockIdx.x & (ca.groups - 1);
-    unsigned long long *c = ctr + CTR_STRIDE * x;
-    const uint64_t base = ca.base[x];
-    for (uint64_t r = next_run(c, base, lane, x, ca.groups, runs); r < runs;
-         r = next_run(c, base, lane, x, ca.groups, runs)) {
-        const uint32_t end = (uint32_t)min((uint64_t)count, (r + 1) * grab);
-        for (uint32_t idx = (uint32_t)(r * grab); idx < end; ++idx) {
+    BlockClaims bc{ctr + CTR_STRIDE * x, ca.base[x], x, ca.groups, ca.runs,
+                   (uint32_t)__builtin_amdgcn_readfirstlane(threadIdx.x / WAVE), 0u, slot};
+    const uint32_t per_run = WPB * grab;
+    for (uint32_t r = bc.next(lane); r < ca.runs; r = bc.next(lane)) {
+        const uint32_t end = (uint32_t)min((uint64_t)count, ((uint64_t)r + 1) * per_run);
+        for (uint32_t idx = r * per_run + bc.wave; idx < end; idx += WPB) {
             const WaveItem it = sload(items + idx);
             const MatDesc md = sload(mats + it.mat);
             run_item<typename OpsFor<V, N, KAHAN>::type>(it, md, stage, partials, lane);
@@ -662,18 +689,15 @@ void walk_fused(const WaveItem *items, uint32_t count, uint32_t grab,
                                                     double *partials, unsigned long long *ctr,
                                                     CtrArgs ca)
 {
+    __shared__ uint32_t slot[2];
     const int lane = threadIdx.x & (WAVE - 1);
-    // Scalar operations only, so that the counter address and the loop bound
-    // stay in SGPRs (a divide would run on the VALU and hold them in VGPRs,
-    // which the walk needs for its row sums).
-    const uint32_t runs = ca.runs;
     const uint32_t x = blockIdx.x & (ca.groups - 1);
-    unsigned long long *c = ctr + CTR_STRIDE * x;
-    const uint64_t base = ca.base[x];
-    for (uint64_t r = next_run(c, base, lane, x, ca.groups, runs); r < runs;
-         r = next_run(c, base, lane, x, ca.groups, runs)) {
-        const uint32_t end = (uint32_t)min((uint64_t)count, (r + 1) * grab);
-        for (uint32_t idx = (uint32_t)(r * grab); idx < end; ++idx) {
+    BlockClaims bc{ctr + CTR_STRIDE * x, ca.base[x], x, ca.groups, ca.runs,
+                   (uint32_t)__builtin_amdgcn_readfirstlane(threadIdx.x / WAVE), 0u, slot};
+    const uint32_t per_run = WPB * grab;
+    for (uint32_t r = bc.next(lane); r < ca.runs; r = bc.next(lane)) {
+        const uint32_t end = (uint32_t)min((uint64_t)count, ((uint64_t)r + 1) * per_run);
+        for (uint32_t idx = r * per_run + bc.wave; idx < end; idx += WPB) {
             const WaveItem it = sload(items + idx);
             const MatDesc md = sload(mats + it.mat);
             run_fused<KAHAN>(std::make_integer_sequence<int, NF>{}, md.n, md.variant, it, md,

@@ -89,7 +89,7 @@ static void check_plan(const perm_ctx *ctx, const std::vector<MatIn> &in, const 
             const MatIn &a = in[w.mat];
             if (!g.fused) CHECK(a.variant == g.variant && a.n == g.n, "mixed group");
             else CHECK(a.variant != V_MONT && a.n <= g.nmax_fused, "fused bucket");
-            const uint64_t work = ((uint64_t)w.nlanes << w.log2L) * (uint64_t)a.n;
+            const uint64_t work = ((uint64_t)w.nlanes << w.log2L) * step_cost(a.variant, a.n);
             CHECK(work <= prev, "group not sorted largest first");
             prev = work;
         }

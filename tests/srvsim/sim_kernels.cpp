@@ -62,13 +62,14 @@ int launch_walk(int, int, bool, bool, int, const WaveItem *d_items, uint32_t cou
 {
     if (grab < 1 || !state) return 1;
     if (grid_blocks < 1) grid_blocks = 1;
-    const uint64_t runs = ((uint64_t)count + grab - 1) / grab;
+    const uint64_t per_run = (uint64_t)(BLOCK / WAVE) * grab;
+    const uint64_t runs = ((uint64_t)count + per_run - 1) / per_run;
     const uint32_t groups = ctr_groups(grid_blocks);
     CtrState before = *state;
     for (uint32_t x = 0; x < groups; ++x) {
         const uint64_t runs_x = runs > x ? (runs - x + groups - 1) / groups : 0;
         const uint64_t blocks_x = ((uint64_t)grid_blocks - x + groups - 1) / groups;
-        state->base[x] += runs_x + blocks_x * (BLOCK / WAVE);
+        state->base[x] += runs_x + blocks_x;
     }
     sim_enqueue((hipStream_t)stream, [=] {
         for (uint32_t x = 0; x < groups; ++x) {
@@ -76,16 +77,16 @@ int launch_walk(int, int, bool, bool, int, const WaveItem *d_items, uint32_t cou
             const uint64_t base = before.base[x];
             uint64_t v = *c;
             if (v != base) sim_desync++;
-            long waves = (long)(((uint64_t)grid_blocks - x + groups - 1) / groups) * (BLOCK / WAVE);
-            while (waves > 0) {
+            long blocks = (long)(((uint64_t)grid_blocks - x + groups - 1) / groups);
+            while (blocks > 0) {
                 const uint64_t r = x + (uint64_t)groups * (uint32_t)(v - base);
                 ++v;
                 if (r >= runs) {
-                    --waves;
+                    --blocks;
                     continue;
                 }
-                const uint64_t end = std::min<uint64_t>(count, (r + 1) * grab);
-                for (uint64_t idx = r * grab; idx < end; ++idx) {
+                const uint64_t end = std::min<uint64_t>(count, (r + 1) * per_run);
+                for (uint64_t idx = r * per_run; idx < end; ++idx) {
                     const WaveItem &w = d_items[idx];
                     const MatDesc &d = d_mats[w.mat];
                     uint64_t *slot = (uint64_t *)((char *)partials + 16 * (size_t)w.slot);
@@ -159,8 +160,8 @@ int log2_chunk_for(const perm_ctx *, int variant, int n)
     }
     if (n < 14) return std::max(3, n - 7);
     if (n < 16) return n - 9;
-    if (n <= 20) return n - 8;
-    return n <= 22 ? 12 : 10;
+    if (n <= 17) return n - 8;
+    return n <= 22 ? std::min(n - 9, 11) : 10;
 }
 
 }  // namespace permi
