@@ -135,10 +135,14 @@ struct Chains {
     static constexpr int K = N < 4 ? N : 4;
 };
 
+// Column entries held in SGPRs between steps (at most 80 of the 102 SGPRs).
+constexpr int PF_MAX = 40;
+
 // Row sums as binary64 values, common to the c128, f64 and F_p (Barrett)
 // variants.  E = doubles per entry (2 for complex, 1 for real).  The staged
-// buffer holds [+2A columns][-2A columns], each column n*E doubles.
-template <int N, int E>
+// buffer holds [+2A columns][-2A columns], each column n*E doubles.  PFN
+// column entries are prefetched per step (0: none).
+template <int N, int E, int PFN>
 struct RealRows {
     double r[N * E];
     const char *cols;
@@ -168,6 +172,23 @@ struct RealRows {
 #pragma unroll
         for (int i = 0; i < N * E; ++i) r[i] += c[i];
     }
+    // Software pipelining of the column loads: the first PF entries of the
+    // next step's column are loaded into SGPRs while this step's product is
+    // formed, and flip_pf adds them (loading the rest, if any, directly).
+    static constexpr int PF = PFN;
+    double pf[PF > 0 ? PF : 1];
+    __device__ __forceinline__ void prefetch(sptr<double> c)
+    {
+#pragma unroll
+        for (int i = 0; i < PF; ++i) pf[i] = c[i];
+    }
+    __device__ __forceinline__ void flip_pf(sptr<double> c)
+    {
+#pragma unroll
+        for (int i = 0; i < PF; ++i) r[i] += pf[i];
+#pragma unroll
+        for (int i = PF; i < N * E; ++i) r[i] += c[i];
+    }
     __device__ __forceinline__ void flip_lane(int k, bool up)
     {
         const double s = up ? 1.0 : -1.0;
@@ -178,9 +199,19 @@ struct RealRows {
 };
 
 // ------------------------------------------------------------------- C128
+// Prefetched column entries per variant, from same-device comparisons: the
+// pipelined walk is faster for c128 when the whole column fits (n <= 20) and
+// for F_p; a partial c128 column (n >= 21) and the f64 walk, whose VGPR
+// budget at its occupancy leaves no room for the earlier loads, run faster
+// without it.
+template <int N>
+struct PfC128 {
+    static constexpr int n = 2 * N <= PF_MAX ? 2 * N : 0;
+};
+
 template <int N, bool KAHAN>
-struct OpsC128 : RealRows<N, 2> {
-    using RealRows<N, 2>::r;
+struct OpsC128 : RealRows<N, 2, PfC128<N>::n> {
+    using RealRows<N, 2, PfC128<N>::n>::r;
     double sr, si, cr, ci;
     double gr, gi, hr, hi;      // the running group of four terms
 
@@ -251,8 +282,8 @@ struct OpsC128 : RealRows<N, 2> {
 
 // -------------------------------------------------------------------- F64
 template <int N, bool KAHAN>
-struct OpsF64 : RealRows<N, 1> {
-    using RealRows<N, 1>::r;
+struct OpsF64 : RealRows<N, 1, 0> {
+    using RealRows<N, 1, 0>::r;
     double s, c;
     double g, h;                // the running group of four terms
 
@@ -324,8 +355,8 @@ __device__ __forceinline__ double reduce_to_range(double v, double p, double pin
 }
 
 template <int N>
-struct OpsModp : RealRows<N, 1> {
-    using RealRows<N, 1>::r;
+struct OpsModp : RealRows<N, 1, (N < PF_MAX ? N : PF_MAX)> {
+    using RealRows<N, 1, (N < PF_MAX ? N : PF_MAX)>::r;
     double s;
     double p, pinv;
 
@@ -420,6 +451,18 @@ struct OpsMont {
 #pragma unroll
         for (int i = 0; i < N; ++i) r[i] = addmod(r[i], c[i], p);
     }
+    static constexpr int PF = N;
+    uint32_t pf[N];                 // the next step's column (see RealRows)
+    __device__ __forceinline__ void prefetch(sptr<uint32_t> c)
+    {
+#pragma unroll
+        for (int i = 0; i < N; ++i) pf[i] = c[i];
+    }
+    __device__ __forceinline__ void flip_pf(sptr<uint32_t>)
+    {
+#pragma unroll
+        for (int i = 0; i < N; ++i) r[i] = addmod(r[i], pf[i], p);
+    }
     __device__ __forceinline__ void flip_lane(int k, bool up)
     {
         sptr<uint32_t> cp = col(k, false);
@@ -479,35 +522,54 @@ template <int N, bool K> struct OpsFor<V_MONT, N, K> { using type = OpsMont<N>; 
 // 4m+3 flip column 1 (down, then up); step 4m+2 flips column 2, down for even
 // m and up for odd m; step 4m flips column b+1 with b = ctz(4m), up exactly
 // when bit b+1 of j is set.
-// Keep each step's instructions (and its column loads) between step
-// boundaries: letting the scheduler pull future steps' scalar loads forward
-// overflows the SGPR file; the load latency is hidden by the other waves.
+// Keep each step's instructions between step boundaries: letting the
+// scheduler pull future steps' scalar loads forward overflows the SGPR file.
+// Instead each step loads the next step's column by hand (prefetch) right
+// after its own adds, so the loads are in flight during its product.
 __device__ __forceinline__ void step_boundary() { __builtin_amdgcn_sched_barrier(0); }
 
+// The column flipped by the first step of group m (0 < m, 4m != L/2).  For
+// 4m = L/2 and 4m = L it still names a column of the matrix (c + 1 <= n - 6,
+// since a wave item never exceeds 2^(n-1) indices): the last group before
+// either prefetches it unconditionally, without a branch that would let the
+// compiler move the step's code past its boundaries, and does not use it.
 template <class Ops>
-__device__ __forceinline__ void group_tail(Ops &S, uint32_t m)
+__device__ __forceinline__ auto first_col(const Ops &S, uint32_t m)
 {
-    S.template gterm<0>();
-    step_boundary();
-    S.flip(S.col(1, true));
-    S.template gterm<1>();
-    step_boundary();
-    S.flip(S.col(2, !(m & 1)));
-    S.template gterm<2>();
-    step_boundary();
-    S.flip(S.col(1, false));
-    S.template gterm<3>();
+    const uint32_t j = m << 2;
+    const uint32_t b = __builtin_ctz(j);
+    return S.col(b + 1, !((j >> (b + 1)) & 1));
+}
+
+// One Gray step: add the prefetched column `cur`, start loading `nxt`, then
+// form the term.
+template <int Q, class Ops, class C>
+__device__ __forceinline__ void pstep(Ops &S, C cur, C nxt)
+{
+    S.flip_pf(cur);
+    S.prefetch(nxt);
+    if (Ops::PF > 0) step_boundary();   // the loads go out before the product
+    S.template gterm<Q>();
     step_boundary();
 }
 
+// Steps 4m+1 .. 4m+3; the last one prefetches `nxt`, the column of the next
+// group's first step.
+template <class Ops, class C>
+__device__ __forceinline__ void group_rest(Ops &S, uint32_t m, C nxt)
+{
+    pstep<1>(S, S.col(1, true), S.col(2, !(m & 1)));
+    pstep<2>(S, S.col(2, !(m & 1)), S.col(1, false));
+    pstep<3>(S, S.col(1, false), nxt);
+}
+
+// Group m (0 < m, 4m != L/2).
 template <class Ops>
 __device__ __forceinline__ void group(Ops &S, const char *cols, uint32_t m)
 {
     S.cols = opaque(cols);
-    const uint32_t j = m << 2;
-    const uint32_t b = __builtin_ctz(j);
-    S.flip(S.col(b + 1, !((j >> (b + 1)) & 1)));
-    group_tail(S, m);
+    pstep<0>(S, first_col(S, m), S.col(1, true));
+    group_rest(S, m, first_col(S, m + 1));
 }
 
 // One lane: seed at xl, then the 2^c - 1 Gray steps of its chunk.
@@ -519,13 +581,20 @@ __device__ __forceinline__ void walk_lane(Ops &S, uint64_t xl, uint32_t c)
     if (c >= 3) {
         const uint32_t G = 1u << (c - 2);      // groups of four steps
         const uint32_t H = G >> 1;             // the group holding j = L/2
-        group_tail(S, 0);
+        // group 0: step 0 is the seed's own term
+        S.prefetch(S.col(1, true));
+        S.template gterm<0>();
+        step_boundary();
+        group_rest(S, 0, first_col(S, 1));
 #pragma unroll 1
         for (uint32_t m = 1; m < H; ++m) group(S, cols, m);
         // j = L/2: column c, direction from bit c of the lane's start index.
         S.cols = opaque(cols);
         S.flip_lane(c, (xl >> c) & 1);
-        group_tail(S, H);
+        S.prefetch(S.col(1, true));
+        S.template gterm<0>();
+        step_boundary();
+        group_rest(S, H, first_col(S, H + 1));
 #pragma unroll 1
         for (uint32_t m = H + 1; m < G; ++m) group(S, cols, m);
     } else {
