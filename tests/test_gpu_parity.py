@@ -221,3 +221,33 @@ def test_batch_device_path_and_bad_item(P, ctx):
     with pytest.raises(P.PermError) as e:
         P.perm_batch(ctx, items, data)
     assert e.value.status == P.PERM_EINVAL and "item 2" in str(e.value)
+
+
+# ------------------------------------------------------- persistent claims
+@pytest.mark.parametrize("count", [1, 2, 3, 5, 9, 13, 21, 29, 33])
+def test_block_claims_small_grids(P, ctx, O, count):
+    """One wave item per matrix (c128, n = 12): 1..33 items launch grids of
+    1..9 blocks, so the work counters run in groups of 1, 2, 4 and 8 (the
+    largest power of two not above the grid) and a block's last run of four
+    items is partly empty.  Every result equals the single-matrix call bit
+    for bit and the oracle within tolerance."""
+    g = E.rng(12, count)
+    mats = [(E.ginibre_complex(12, g), "c128", 0) for _ in range(count)]
+    items, data = P.pack_matrices(mats)
+    vals = P.batch_values(items, P.perm_batch(ctx, items, data))
+    for (A, _, _), v in zip(mats, vals):
+        assert v == P.perm_c128(ctx, A)
+        assert abs(v - O.native.ryser_c128(A)) <= TOL * scale(A)
+
+
+def test_multi_item_claims_tiny_matrices(P, ctx, O):
+    """140,000 f64 matrices of order 5 (one 16-lane item each): items far
+    outnumber resident waves, so blocks claim several items per wave at a
+    time.  All agree with the oracle."""
+    g = E.rng(13, 0)
+    A5 = g.standard_normal((140000, 5, 5))
+    mats = [(a, "f64", 0) for a in A5]
+    items, data = P.pack_matrices(mats)
+    vals = P.batch_values(items, P.perm_batch(ctx, items, data))
+    for a, v in zip(A5, vals):
+        assert abs(v - O.native.ryser_f64(a)) <= TOL * scale(a)
