@@ -125,10 +125,12 @@ struct CtrArgs {                 // kernel argument (by value)
     uint32_t runs;               // ceil(count / grab), computed on the host
 };
 
-// Blocks claim runs of (BLOCK / WAVE) * grab consecutive items per atomic
-// (grab >= 1), the block's waves taking every (BLOCK / WAVE)-th item of the
-// run: tiny items would otherwise make the claims the bottleneck.  `state`
-// holds the counters' values before the launch and is advanced past it.
+// Items are walked in runs of (BLOCK / WAVE) * grab consecutive items
+// (grab >= 1), the block's waves taking every (BLOCK / WAVE)-th item of a
+// run: block b walks run b first, then claims runs with one atomic each
+// (several items per run keep tiny items from making the claims the
+// bottleneck).  `state` holds the counters' values before the launch and
+// is advanced past it.
 int launch_walk(int variant, int n, bool kahan, bool fused, int nmax_fused,
                 const WaveItem *d_items, uint32_t count, uint32_t grab, const MatDesc *d_mats,
                 const void *stage, double *partials, unsigned long long *ctr,

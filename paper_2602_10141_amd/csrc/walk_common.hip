@@ -206,14 +206,12 @@ int launch_walk(int variant, int n, bool kahan, bool fused, int nmax_fused, cons
     hipError_t e = hipLaunchKernel((const void *)f, dim3(grid_blocks), dim3(BLOCK), args, 0,
                                    (hipStream_t)stream);
     if (e != hipSuccess) return (int)e;
-    // Counter x: one claim per run r = x (mod groups), plus the one failing
-    // claim of every block b = x (mod groups).
+    // Block b walks run b without a claim.  With more runs than blocks,
+    // counter x then takes one claim per remaining run r = x (mod groups)
+    // and one failing claim per block b = x (mod groups): runs_x in all.
     const uint64_t g = ca.groups;
-    for (uint64_t x = 0; x < g; ++x) {
-        const uint64_t runs_x = runs > x ? (runs - x + g - 1) / g : 0;
-        const uint64_t blocks_x = ((uint64_t)grid_blocks - x + g - 1) / g;
-        state->base[x] += runs_x + blocks_x;
-    }
+    if (runs > (uint64_t)grid_blocks)
+        for (uint64_t x = 0; x < g; ++x) state->base[x] += runs > x ? (runs - x + g - 1) / g : 0;
     return (int)hipGetLastError();
 }
 

@@ -665,35 +665,36 @@ struct Occupancy {
                     : (N > 40 ? 3 : 4);
 };
 
-// Next run of items for this block's counter group, or `runs` (= none left).
-__device__ __forceinline__ uint32_t next_run(unsigned long long *c, uint64_t base, int lane,
-                                             uint32_t x, uint32_t groups, uint32_t runs)
-{
-    const uint64_t r = x + (uint64_t)groups * next_item(c, base, lane);
-    return r < runs ? (uint32_t)r : runs;
-}
-
-// Block-level claims.  Wave 0 of a block claims a run of WPB * grab
-// consecutive wave items and publishes it in LDS; wave w takes the items
-// w, w + WPB, w + 2 WPB, ... of the run.  Consecutive items belong to the
-// same matrix (the host orders them so), so the four waves of a block walk
-// one matrix side by side and its columns are shared in the CU's scalar
-// cache; with one claim per wave, the waves of a CU walked as many different
-// matrices as there were waves and the scalar cache missed on about half of
-// the column loads in batches.  The LDS slot is double-buffered: the slot
-// written for claim i + 2 is read for claim i before every wave passes the
-// barrier of claim i + 1, so one barrier per claim suffices.
+// Block-level claims.  Block b first walks run b (the grid never exceeds the
+// number of runs), so a launch with no more runs than blocks, such as one
+// small matrix, makes no atomic at all; in a larger launch wave 0 of the
+// block then claims further runs of WPB * grab consecutive wave items from
+// its counter and publishes each in LDS.  Wave w takes the items w, w + WPB,
+// w + 2 WPB, ... of a run.  Consecutive items belong to the same matrix (the
+// host orders them so), so the four waves of a block walk one matrix side by
+// side and its columns are shared in the CU's scalar cache; with one claim
+// per wave, the waves of a CU walked as many different matrices as there
+// were waves and the scalar cache missed on about half of the column loads
+// in batches.  Counter x (of `groups`, serving the blocks b = x mod groups)
+// hands out the runs x + groups * (nb + k), k = 0, 1, ..., where nb is the
+// number of blocks in group x (their first runs were static).  The LDS slot
+// is double-buffered: the slot written for claim i + 2 is read for claim i
+// before every wave passes the barrier of claim i + 1, so one barrier per
+// claim suffices.
 constexpr uint32_t WPB = BLOCK / WAVE;
 
 struct BlockClaims {
     unsigned long long *c;
     uint64_t base;
-    uint32_t x, groups, runs, wave, parity;
+    uint32_t x, groups, nb, runs, wave, parity;
     uint32_t *slot;                 // two uint32 in LDS
 
     __device__ __forceinline__ uint32_t next(int lane)
     {
-        if (wave == 0) slot[parity] = next_run(c, base, lane, x, groups, runs);
+        if (wave == 0) {
+            const uint64_t r = x + (uint64_t)groups * (nb + next_item(c, base, lane));
+            slot[parity] = r < runs ? (uint32_t)r : runs;
+        }
         __syncthreads();
         const uint32_t r = __builtin_amdgcn_readfirstlane(slot[parity]);
         parity ^= 1u;
@@ -701,9 +702,29 @@ struct BlockClaims {
     }
 };
 
-// Persistent kernel: blocks claim runs (largest items first, as ordered by
-// the host) until the counter passes the number of runs.  W > 0 overrides
-// the waves-per-SIMD target (used when tuning the budgets).
+// Scalar operations only, so that the counter address and the loop bounds
+// stay in SGPRs (a divide would run on the VALU and hold them in VGPRs,
+// which the walk needs for its row sums); groups is a power of two.
+__device__ __forceinline__ BlockClaims block_claims(unsigned long long *ctr, const CtrArgs &ca,
+                                                    uint32_t *slot)
+{
+    const uint32_t x = blockIdx.x & (ca.groups - 1);
+    const uint32_t nb = (gridDim.x - x + ca.groups - 1) >> __builtin_ctz(ca.groups);
+    return BlockClaims{ctr + CTR_STRIDE * x, ca.base[x], x, ca.groups, nb, ca.runs,
+                       (uint32_t)__builtin_amdgcn_readfirstlane(threadIdx.x / WAVE), 0u, slot};
+}
+
+// Walk the runs of this block: the static first one, then claimed ones (one
+// loop, so that the walk's code is instantiated once).
+template <class F>
+__device__ __forceinline__ void for_each_run(BlockClaims &bc, int lane, F &&walk_run)
+{
+    const bool claims = bc.runs > gridDim.x;
+    for (uint32_t r = blockIdx.x; r < bc.runs; r = claims ? bc.next(lane) : bc.runs) walk_run(r);
+}
+
+// Persistent kernel over the host's item list (largest items first).  W > 0
+// overrides the waves-per-SIMD target (used when tuning the budgets).
 template <int V, int N, bool KAHAN, int W = 0>
 __global__ __launch_bounds__(BLOCK)
 __attribute__((amdgpu_waves_per_eu(W > 0 ? W : Occupancy<V, N>::waves, 8)))
@@ -714,21 +735,17 @@ void walk_kernel(const WaveItem *items, uint32_t count, uint32_t grab,
 {
     __shared__ uint32_t slot[2];
     const int lane = threadIdx.x & (WAVE - 1);
-    // Scalar operations only, so that the counter address and the loop bound
-    // stay in SGPRs (a divide would run on the VALU and hold them in VGPRs,
-    // which the walk needs for its row sums).
-    const uint32_t x = blockIdx.x & (ca.groups - 1);
-    BlockClaims bc{ctr + CTR_STRIDE * x, ca.base[x], x, ca.groups, ca.runs,
-                   (uint32_t)__builtin_amdgcn_readfirstlane(threadIdx.x / WAVE), 0u, slot};
+    BlockClaims bc = block_claims(ctr, ca, slot);
     const uint32_t per_run = WPB * grab;
-    for (uint32_t r = bc.next(lane); r < ca.runs; r = bc.next(lane)) {
+    for_each_run(bc, lane, [&](uint32_t r) __attribute__((always_inline)) {
+        r = __builtin_amdgcn_readfirstlane(r);
         const uint32_t end = (uint32_t)min((uint64_t)count, ((uint64_t)r + 1) * per_run);
         for (uint32_t idx = r * per_run + bc.wave; idx < end; idx += WPB) {
             const WaveItem it = sload(items + idx);
             const MatDesc md = sload(mats + it.mat);
             run_item<typename OpsFor<V, N, KAHAN>::type>(it, md, stage, partials, lane);
         }
-    }
+    });
 }
 
 // Fused kernel: any mix of c128 / f64 / F_p (Barrett) matrices of order <= NF.
@@ -760,11 +777,10 @@ void walk_fused(const WaveItem *items, uint32_t count, uint32_t grab,
 {
     __shared__ uint32_t slot[2];
     const int lane = threadIdx.x & (WAVE - 1);
-    const uint32_t x = blockIdx.x & (ca.groups - 1);
-    BlockClaims bc{ctr + CTR_STRIDE * x, ca.base[x], x, ca.groups, ca.runs,
-                   (uint32_t)__builtin_amdgcn_readfirstlane(threadIdx.x / WAVE), 0u, slot};
+    BlockClaims bc = block_claims(ctr, ca, slot);
     const uint32_t per_run = WPB * grab;
-    for (uint32_t r = bc.next(lane); r < ca.runs; r = bc.next(lane)) {
+    for_each_run(bc, lane, [&](uint32_t r) __attribute__((always_inline)) {
+        r = __builtin_amdgcn_readfirstlane(r);
         const uint32_t end = (uint32_t)min((uint64_t)count, ((uint64_t)r + 1) * per_run);
         for (uint32_t idx = r * per_run + bc.wave; idx < end; idx += WPB) {
             const WaveItem it = sload(items + idx);
@@ -772,7 +788,7 @@ void walk_fused(const WaveItem *items, uint32_t count, uint32_t grab,
             run_fused<KAHAN>(std::make_integer_sequence<int, NF>{}, md.n, md.variant, it, md,
                              stage, partials, lane);
         }
-    }
+    });
 }
 
 // ------------------------------------------------ instantiation tables

@@ -66,34 +66,39 @@ int launch_walk(int, int, bool, bool, int, const WaveItem *d_items, uint32_t cou
     const uint64_t runs = ((uint64_t)count + per_run - 1) / per_run;
     const uint32_t groups = ctr_groups(grid_blocks);
     CtrState before = *state;
-    for (uint32_t x = 0; x < groups; ++x) {
-        const uint64_t runs_x = runs > x ? (runs - x + groups - 1) / groups : 0;
-        const uint64_t blocks_x = ((uint64_t)grid_blocks - x + groups - 1) / groups;
-        state->base[x] += runs_x + blocks_x;
-    }
+    const bool dynamic = runs > (uint64_t)grid_blocks;
+    if (dynamic)
+        for (uint32_t x = 0; x < groups; ++x)
+            state->base[x] += runs > x ? (runs - x + groups - 1) / groups : 0;
     sim_enqueue((hipStream_t)stream, [=] {
-        for (uint32_t x = 0; x < groups; ++x) {
+        auto walk_run = [&](uint64_t r) {
+            const uint64_t end = std::min<uint64_t>(count, (r + 1) * per_run);
+            for (uint64_t idx = r * per_run; idx < end; ++idx) {
+                const WaveItem &w = d_items[idx];
+                const MatDesc &d = d_mats[w.mat];
+                uint64_t *slot = (uint64_t *)((char *)partials + 16 * (size_t)w.slot);
+                slot[0] = *(const uint64_t *)((const char *)stage + d.stage_off);
+                slot[1] = w.x0;
+                sim_items++;
+            }
+        };
+        // block b walks run b, then (more runs than blocks) claims more
+        for (uint64_t b = 0; b < (uint64_t)grid_blocks && b < runs; ++b) walk_run(b);
+        for (uint32_t x = 0; dynamic && x < groups; ++x) {
             unsigned long long *c = ctr + CTR_STRIDE * x;
             const uint64_t base = before.base[x];
             uint64_t v = *c;
             if (v != base) sim_desync++;
-            long blocks = (long)(((uint64_t)grid_blocks - x + groups - 1) / groups);
+            const uint64_t nb = ((uint64_t)grid_blocks - x + groups - 1) / groups;
+            long blocks = (long)nb;
             while (blocks > 0) {
-                const uint64_t r = x + (uint64_t)groups * (uint32_t)(v - base);
+                const uint64_t r = x + (uint64_t)groups * (nb + (uint32_t)(v - base));
                 ++v;
                 if (r >= runs) {
                     --blocks;
                     continue;
                 }
-                const uint64_t end = std::min<uint64_t>(count, (r + 1) * per_run);
-                for (uint64_t idx = r * per_run; idx < end; ++idx) {
-                    const WaveItem &w = d_items[idx];
-                    const MatDesc &d = d_mats[w.mat];
-                    uint64_t *slot = (uint64_t *)((char *)partials + 16 * (size_t)w.slot);
-                    slot[0] = *(const uint64_t *)((const char *)stage + d.stage_off);
-                    slot[1] = w.x0;
-                    sim_items++;
-                }
+                walk_run(r);
             }
             *c = v;
         }
