@@ -451,6 +451,9 @@ int execute(perm_ctx *ctx, Plan &pl, const void *src, void *out, size_t out_slot
     const WaveItem *d_items = (const WaveItem *)((char *)ctx->plan_buf.p + mb);
 
     HIPCHK((hipError_t)launch_stage(d_mats, (int)pl.mats.size(), src, ctx->stage.p, s));
+    int walks = 0;
+    for (const Group &g : pl.groups) walks += g.count > 0;
+    bool finalized = false;
     for (const Group &g : pl.groups) {
         if (!g.count) continue;
         const int occ = occupancy(ctx, g);
@@ -475,18 +478,22 @@ int execute(perm_ctx *ctx, Plan &pl, const void *src, void *out, size_t out_slot
             }
             HIPCHK(hipEventRecord(ev.first, s));
         }
+        // a single one-block walk finalizes the call's matrices itself
+        const bool fin = walks == 1 && grid == 1;
         HIPCHK((hipError_t)launch_walk(g.variant, g.n, g.kahan, g.fused, g.nmax_fused,
                                        d_items + g.first_item, g.count, grab, d_mats, ctx->stage.p,
                                        (double *)ctx->partials.p,
                                        (unsigned long long *)ctx->ctr.p, &ctx->ctr_state, grid,
-                                       s));
+                                       s, fin ? out : nullptr, fin ? (int)pl.mats.size() : 0));
+        finalized = finalized || fin;
         if (ctx->prof_on) {
             HIPCHK(hipEventRecord(ev.second, s));
             ctx->prof_pending.push_back(ev);
         }
     }
-    HIPCHK((hipError_t)launch_finalize(d_mats, (int)pl.mats.size(), (const double *)ctx->partials.p,
-                                       out, s));
+    if (!finalized)
+        HIPCHK((hipError_t)launch_finalize(d_mats, (int)pl.mats.size(),
+                                           (const double *)ctx->partials.p, out, s));
     return PERM_OK;
 }
 

@@ -63,88 +63,12 @@ __global__ __launch_bounds__(256) void stage_kernel(const MatDesc *mats, const c
 }
 
 // ---------------------------------------------------------------- finalize
-__device__ uint64_t powmod_u64(uint64_t b, uint32_t e, uint64_t p)
-{
-    uint64_t r = 1 % p;
-    b %= p;
-    while (e) {
-        if (e & 1) r = (r * b) % p;
-        b = (b * b) % p;
-        e >>= 1;
-    }
-    return r;
-}
-
 __global__ __launch_bounds__(256) void finalize_kernel(const MatDesc *mats, const double *partials,
                                                        char *out)
 {
     __shared__ double sa[256], sb[256];
     __shared__ unsigned long long su[256];
-    const MatDesc md = mats[blockIdx.x];
-    const int t = threadIdx.x;
-    const bool modp = md.variant == V_MODP || md.variant == V_MONT;
-    char *o = out + 16 * (size_t)md.out_slot;
-
-    if (md.num_parts == 0) {                // n = 0: the empty permanent is 1
-        if (t == 0) {
-            if (modp) {
-                ((uint32_t *)o)[0] = 1u % md.p;
-                ((uint32_t *)o)[1] = ((uint32_t *)o)[2] = ((uint32_t *)o)[3] = 0u;
-            } else {
-                ((double *)o)[0] = 1.0;
-                ((double *)o)[1] = 0.0;
-            }
-        }
-        return;
-    }
-    if (modp) {
-        const uint64_t P = md.p;
-        uint64_t acc = 0;
-        for (uint32_t q = t; q < md.num_parts; q += 256) {
-            acc += (uint64_t)partials[2 * ((size_t)md.first_part + q)];
-            if (acc >= (1ull << 62)) acc %= P;
-        }
-        su[t] = acc % P;
-        __syncthreads();
-        for (int w = 128; w >= 1; w >>= 1) {
-            if (t < w) su[t] = (su[t] + su[t + w]) % P;
-            __syncthreads();
-        }
-        if (t == 0) {
-            uint64_t v = su[0];
-            // Montgomery products leave R^{-(n-1)}; Glynn leaves 2^{n-1}.
-            uint64_t f = 1;
-            if (md.variant == V_MONT) f = powmod_u64((1ull << 32) % P, md.n - 1, P);
-            if (!(md.flags & MD_NO_SCALE)) f = (f * powmod_u64((P + 1) / 2, md.n - 1, P)) % P;
-            v = (v * f) % P;
-            ((uint32_t *)o)[0] = (uint32_t)v;
-            ((uint32_t *)o)[1] = ((uint32_t *)o)[2] = ((uint32_t *)o)[3] = 0u;
-        }
-        return;
-    }
-    // Floats: per-thread compensated sums over a fixed stride, then a fixed tree.
-    double s0 = 0.0, c0 = 0.0, s1 = 0.0, c1 = 0.0;
-    for (uint32_t q = t; q < md.num_parts; q += 256) {
-        const double *pp = partials + 2 * ((size_t)md.first_part + q);
-        kahan_add(s0, c0, pp[0]);
-        kahan_add(s1, c1, pp[1]);
-    }
-    sa[t] = s0 - c0;
-    sb[t] = s1 - c1;
-    __syncthreads();
-    for (int w = 128; w >= 1; w >>= 1) {
-        if (t < w) { sa[t] += sa[t + w]; sb[t] += sb[t + w]; }
-        __syncthreads();
-    }
-    if (t == 0) {
-        double a = sa[0], b = sb[0];
-        if (!(md.flags & MD_NO_SCALE)) {
-            a = __builtin_ldexp(a, -(md.n - 1));
-            b = __builtin_ldexp(b, -(md.n - 1));
-        }
-        ((double *)o)[0] = a;
-        ((double *)o)[1] = md.variant == V_C128 ? b : 0.0;
-    }
+    finalize_one(mats[blockIdx.x], partials, out, sa, sb, su);
 }
 
 // ---------------------------------------------------------- host launchers
@@ -189,16 +113,20 @@ int walk_occupancy(int variant, int n, bool kahan, bool fused, int nmax_fused, i
 int launch_walk(int variant, int n, bool kahan, bool fused, int nmax_fused, const WaveItem *d_items,
                 uint32_t count, uint32_t grab, const MatDesc *d_mats, const void *stage,
                 double *partials, unsigned long long *ctr, CtrState *state, int grid_blocks,
-                void *stream)
+                void *stream, void *fin_out, int fin_nmats)
 {
     WalkFn f = pick(variant, n, kahan, fused, nmax_fused);
     if (!f || grab < 1 || !state) return (int)hipErrorInvalidValue;
     if (grid_blocks < 1) grid_blocks = 1;
+    if (fin_nmats < 0 || (fin_nmats > 0 && (grid_blocks != 1 || !fin_out)))
+        return (int)hipErrorInvalidValue;
     const uint64_t per_run = (uint64_t)(BLOCK / WAVE) * grab;
     const uint64_t runs = ((uint64_t)count + per_run - 1) / per_run;
     CtrArgs ca{};
     ca.groups = ctr_groups(grid_blocks);
     ca.runs = (uint32_t)runs;
+    ca.fin_out = (char *)fin_out;
+    ca.fin_nmats = (uint32_t)fin_nmats;
     for (int x = 0; x < CTR_GROUPS; ++x) ca.base[x] = state->base[x];
     const char *st = (const char *)stage;
     void *args[] = {(void *)&d_items, (void *)&count, (void *)&grab, (void *)&d_mats, (void *)&st,

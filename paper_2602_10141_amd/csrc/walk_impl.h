@@ -665,6 +665,96 @@ struct Occupancy {
                     : (N > 40 ? 3 : 4);
 };
 
+// ---------------------------------------------------------------- finalize
+// Per matrix, with the 256 threads of a block: reduce its partial slots in a
+// fixed order (strided compensated sums, then a fixed tree), apply
+// 2^{-(n-1)} (floats) or inv(2)^{n-1} (F_p; Montgomery's R^{-(n-1)} too),
+// write the 16-byte result slot.  Shared by finalize_kernel and by walk
+// launches of one block, which finalize their own matrices, so the two give
+// identical bits.  sa, sb, su: 256 entries each in LDS.
+__device__ inline uint64_t powmod_u64(uint64_t b, uint32_t e, uint64_t p)
+{
+    uint64_t r = 1 % p;
+    b %= p;
+    while (e) {
+        if (e & 1) r = (r * b) % p;
+        b = (b * b) % p;
+        e >>= 1;
+    }
+    return r;
+}
+
+static_assert(BLOCK == 256, "finalize_one reduces with 256 threads");
+__device__ inline void finalize_one(const MatDesc md, const double *partials, char *out,
+                                    double *sa, double *sb, unsigned long long *su)
+{
+    const int t = threadIdx.x;
+    const bool modp = md.variant == V_MODP || md.variant == V_MONT;
+    char *o = out + 16 * (size_t)md.out_slot;
+
+    if (md.num_parts == 0) {                // n = 0: the empty permanent is 1
+        if (t == 0) {
+            if (modp) {
+                ((uint32_t *)o)[0] = 1u % md.p;
+                ((uint32_t *)o)[1] = ((uint32_t *)o)[2] = ((uint32_t *)o)[3] = 0u;
+            } else {
+                ((double *)o)[0] = 1.0;
+                ((double *)o)[1] = 0.0;
+            }
+        }
+        return;
+    }
+    if (modp) {
+        const uint64_t P = md.p;
+        uint64_t acc = 0;
+        for (uint32_t q = t; q < md.num_parts; q += 256) {
+            acc += (uint64_t)partials[2 * ((size_t)md.first_part + q)];
+            if (acc >= (1ull << 62)) acc %= P;
+        }
+        su[t] = acc % P;
+        __syncthreads();
+        for (int w = 128; w >= 1; w >>= 1) {
+            if (t < w) su[t] = (su[t] + su[t + w]) % P;
+            __syncthreads();
+        }
+        if (t == 0) {
+            uint64_t v = su[0];
+            // Montgomery products leave R^{-(n-1)}; Glynn leaves 2^{n-1}.
+            uint64_t f = 1;
+            if (md.variant == V_MONT) f = powmod_u64((1ull << 32) % P, md.n - 1, P);
+            if (!(md.flags & MD_NO_SCALE)) f = (f * powmod_u64((P + 1) / 2, md.n - 1, P)) % P;
+            v = (v * f) % P;
+            ((uint32_t *)o)[0] = (uint32_t)v;
+            ((uint32_t *)o)[1] = ((uint32_t *)o)[2] = ((uint32_t *)o)[3] = 0u;
+        }
+        return;
+    }
+    // Floats: per-thread compensated sums over a fixed stride, then a fixed tree.
+    double s0 = 0.0, c0 = 0.0, s1 = 0.0, c1 = 0.0;
+    for (uint32_t q = t; q < md.num_parts; q += 256) {
+        const double *pp = partials + 2 * ((size_t)md.first_part + q);
+        kahan_add(s0, c0, pp[0]);
+        kahan_add(s1, c1, pp[1]);
+    }
+    sa[t] = s0 - c0;
+    sb[t] = s1 - c1;
+    __syncthreads();
+    for (int w = 128; w >= 1; w >>= 1) {
+        if (t < w) { sa[t] += sa[t + w]; sb[t] += sb[t + w]; }
+        __syncthreads();
+    }
+    if (t == 0) {
+        double a = sa[0], b = sb[0];
+        if (!(md.flags & MD_NO_SCALE)) {
+            a = __builtin_ldexp(a, -(md.n - 1));
+            b = __builtin_ldexp(b, -(md.n - 1));
+        }
+        ((double *)o)[0] = a;
+        ((double *)o)[1] = md.variant == V_C128 ? b : 0.0;
+    }
+}
+
+
 // Block-level claims.  Block b first walks run b (the grid never exceeds the
 // number of runs), so a launch with no more runs than blocks, such as one
 // small matrix, makes no atomic at all; in a larger launch wave 0 of the
@@ -723,6 +813,21 @@ __device__ __forceinline__ void for_each_run(BlockClaims &bc, int lane, F &&walk
     for (uint32_t r = blockIdx.x; r < bc.runs; r = claims ? bc.next(lane) : bc.runs) walk_run(r);
 }
 
+// A launch of one block finalizes its own matrices (after every wave's
+// partials are stored), saving the finalize launch for a single small
+// matrix.
+__device__ __forceinline__ void finalize_in_walk(const CtrArgs &ca, const MatDesc *mats,
+                                                 const double *partials)
+{
+    if (!ca.fin_nmats) return;
+    __shared__ double sa[256], sb[256];
+    __shared__ unsigned long long su[256];
+    for (uint32_t m = 0; m < ca.fin_nmats; ++m) {
+        __syncthreads();
+        finalize_one(mats[m], partials, ca.fin_out, sa, sb, su);
+    }
+}
+
 // Persistent kernel over the host's item list (largest items first).  W > 0
 // overrides the waves-per-SIMD target (used when tuning the budgets).
 template <int V, int N, bool KAHAN, int W = 0>
@@ -746,6 +851,7 @@ void walk_kernel(const WaveItem *items, uint32_t count, uint32_t grab,
             run_item<typename OpsFor<V, N, KAHAN>::type>(it, md, stage, partials, lane);
         }
     });
+    finalize_in_walk(ca, mats, partials);
 }
 
 // Fused kernel: any mix of c128 / f64 / F_p (Barrett) matrices of order <= NF.
@@ -789,6 +895,7 @@ void walk_fused(const WaveItem *items, uint32_t count, uint32_t grab,
                              stage, partials, lane);
         }
     });
+    finalize_in_walk(ca, mats, partials);
 }
 
 // ------------------------------------------------ instantiation tables
