@@ -42,6 +42,12 @@ struct Group {
     uint32_t count;
 };
 
+// Launch shape of one walk group: items per claim and blocks.
+struct LaunchShape {
+    uint32_t grab;
+    int grid;
+};
+
 struct Plan {
     std::vector<permk::MatDesc> mats;
     std::vector<permk::WaveItem> items;
@@ -78,6 +84,7 @@ struct perm_ctx {
     // would otherwise fault in fresh pages on every call)
     std::vector<permi::MatIn> scratch_in;
     permi::Plan scratch_plan;
+    std::vector<permi::LaunchShape> scratch_shape;
     // The last small plan built in scratch_plan, with the chunk length it
     // used per (variant, n): a call with the same inputs and chunk lengths
     // reuses it, and its upload when plan_buf still holds it.

@@ -123,8 +123,9 @@ struct CtrArgs {                 // kernel argument (by value)
     uint64_t base[CTR_GROUPS];
     uint32_t groups;
     uint32_t runs;               // runs of items, computed on the host
-    char *fin_out;               // one-block launch: finalize fin_nmats
-    uint32_t fin_nmats;          //   matrices into fin_out (else 0)
+    char *fin_out;               // one-block launch: stage fin_nmats matrices
+    const char *fin_src;         //   from fin_src, walk, finalize them into
+    uint32_t fin_nmats;          //   fin_out (else 0)
     uint32_t pad;
 };
 
@@ -134,13 +135,14 @@ struct CtrArgs {                 // kernel argument (by value)
 // (several items per run keep tiny items from making the claims the
 // bottleneck).  `state` holds the counters' values before the launch and
 // is advanced past it.  With fin_nmats > 0 (only for grid_blocks == 1 and the
-// launch's matrices being all of d_mats[0 .. fin_nmats)), the block also
-// does launch_finalize's work for those matrices into fin_out afterwards.
+// call's matrices being all of d_mats[0 .. fin_nmats)), the block also does
+// launch_stage's work (from fin_src) first and launch_finalize's work (into
+// fin_out) last, and the caller launches neither.
 int launch_walk(int variant, int n, bool kahan, bool fused, int nmax_fused,
                 const WaveItem *d_items, uint32_t count, uint32_t grab, const MatDesc *d_mats,
                 const void *stage, double *partials, unsigned long long *ctr,
-                CtrState *state, int grid_blocks, void *stream, void *fin_out = nullptr,
-                int fin_nmats = 0);
+                CtrState *state, int grid_blocks, void *stream, const void *fin_src = nullptr,
+                void *fin_out = nullptr, int fin_nmats = 0);
 
 // Items per atomic claim for items of at most 2^max_log2L steps per lane:
 // enough that one claim is at least 64 lane-steps of walk, at most 16.

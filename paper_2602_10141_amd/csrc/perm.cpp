@@ -450,23 +450,33 @@ int execute(perm_ctx *ctx, Plan &pl, const void *src, void *out, size_t out_slot
     const MatDesc *d_mats = (const MatDesc *)ctx->plan_buf.p;
     const WaveItem *d_items = (const WaveItem *)((char *)ctx->plan_buf.p + mb);
 
-    HIPCHK((hipError_t)launch_stage(d_mats, (int)pl.mats.size(), src, ctx->stage.p, s));
-    int walks = 0;
-    for (const Group &g : pl.groups) walks += g.count > 0;
-    bool finalized = false;
-    for (const Group &g : pl.groups) {
+    // launch shape per group: several items per claim only when there are
+    // many more items than resident waves (a short launch keeps one item
+    // per wave); grid = resident blocks, or fewer for a short launch
+    std::vector<LaunchShape> &shape = ctx->scratch_shape;
+    shape.assign(pl.groups.size(), LaunchShape{0, 0});
+    int walks = 0, last = -1;
+    for (size_t q = 0; q < pl.groups.size(); ++q) {
+        const Group &g = pl.groups[q];
         if (!g.count) continue;
         const int occ = occupancy(ctx, g);
         const int per_cu = ctx->grid_per_cu > 0 ? std::min(ctx->grid_per_cu, occ) : occ;
         uint32_t max_l2 = 0;
-        for (uint32_t q = 0; q < g.count; ++q) max_l2 = std::max(max_l2, pl.items[g.first_item + q].log2L);
-        // several items per claim only when there are many more items than
-        // resident waves (a short launch keeps one item per wave)
+        for (uint32_t i = 0; i < g.count; ++i) max_l2 = std::max(max_l2, pl.items[g.first_item + i].log2L);
         const uint32_t resident = (uint32_t)(per_cu * ctx->num_cus * (BLOCK / WAVE));
         const uint32_t grab = std::max(1u, std::min(grab_for(max_l2), g.count / (2 * resident)));
-        const uint32_t runs = (g.count + grab - 1) / grab;
-        const int blocks_needed = (int)((runs + (BLOCK / WAVE) - 1) / (BLOCK / WAVE));
-        const int grid = std::max(1, std::min(blocks_needed, per_cu * ctx->num_cus));
+        const uint32_t runs = (g.count + grab * (BLOCK / WAVE) - 1) / (grab * (BLOCK / WAVE));
+        shape[q] = LaunchShape{grab, (int)std::max(1u, std::min(runs, (uint32_t)(per_cu * ctx->num_cus)))};
+        ++walks;
+        last = (int)q;
+    }
+    // a call that is one walk of one block stages and finalizes in that block
+    const bool one_block = walks == 1 && shape[last].grid == 1;
+    if (!one_block)
+        HIPCHK((hipError_t)launch_stage(d_mats, (int)pl.mats.size(), src, ctx->stage.p, s));
+    for (size_t q = 0; q < pl.groups.size(); ++q) {
+        const Group &g = pl.groups[q];
+        if (!g.count) continue;
         std::pair<hipEvent_t, hipEvent_t> ev{nullptr, nullptr};
         if (ctx->prof_on) {
             if (ctx->prof_pool.empty()) {
@@ -478,20 +488,19 @@ int execute(perm_ctx *ctx, Plan &pl, const void *src, void *out, size_t out_slot
             }
             HIPCHK(hipEventRecord(ev.first, s));
         }
-        // a single one-block walk finalizes the call's matrices itself
-        const bool fin = walks == 1 && grid == 1;
         HIPCHK((hipError_t)launch_walk(g.variant, g.n, g.kahan, g.fused, g.nmax_fused,
-                                       d_items + g.first_item, g.count, grab, d_mats, ctx->stage.p,
-                                       (double *)ctx->partials.p,
-                                       (unsigned long long *)ctx->ctr.p, &ctx->ctr_state, grid,
-                                       s, fin ? out : nullptr, fin ? (int)pl.mats.size() : 0));
-        finalized = finalized || fin;
+                                       d_items + g.first_item, g.count, shape[q].grab, d_mats,
+                                       ctx->stage.p, (double *)ctx->partials.p,
+                                       (unsigned long long *)ctx->ctr.p, &ctx->ctr_state,
+                                       shape[q].grid, s, one_block ? src : nullptr,
+                                       one_block ? out : nullptr,
+                                       one_block ? (int)pl.mats.size() : 0));
         if (ctx->prof_on) {
             HIPCHK(hipEventRecord(ev.second, s));
             ctx->prof_pending.push_back(ev);
         }
     }
-    if (!finalized)
+    if (!one_block)
         HIPCHK((hipError_t)launch_finalize(d_mats, (int)pl.mats.size(),
                                            (const double *)ctx->partials.p, out, s));
     return PERM_OK;

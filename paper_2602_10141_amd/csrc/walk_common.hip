@@ -6,60 +6,9 @@
 namespace permk {
 
 // ----------------------------------------------------------------- staging
-// Staged layout, column-major (column k, row i at k*n + i):
-//   c128, f64, F_p (Barrett): [+2A][-2A] as binary64 (complex: re, im pairs);
-//                             F_p entries are first mapped to balanced
-//                             residues in [-(p-1)/2, (p-1)/2];
-//   F_p (Montgomery):         [2a mod p][(p - 2a) mod p][a][(p - a) mod p] as uint32.
-// Entries of F_p matrices are reduced mod p first.
 __global__ __launch_bounds__(256) void stage_kernel(const MatDesc *mats, const char *src, char *stage)
 {
-    const MatDesc md = mats[blockIdx.x];
-    const int n = md.n;
-    const int nn = n * n;
-    const char *s = src + md.src_off;
-    char *d = stage + md.stage_off;
-    for (int e = threadIdx.x; e < nn; e += blockDim.x) {
-        const int i = e / n;          // source row
-        const int k = e - i * n;      // source column
-        const int t = k * n + i;      // staged: column k, row i
-        switch (md.variant) {
-        case V_C128: {
-            const double *a = (const double *)s + 2 * (size_t)e;
-            double *o = (double *)d;
-            o[2 * t] = 2.0 * a[0];
-            o[2 * t + 1] = 2.0 * a[1];
-            o[2 * nn + 2 * t] = -2.0 * a[0];
-            o[2 * nn + 2 * t + 1] = -2.0 * a[1];
-            break;
-        }
-        case V_F64: {
-            const double a = ((const double *)s)[e];
-            ((double *)d)[t] = 2.0 * a;
-            ((double *)d)[nn + t] = -2.0 * a;
-            break;
-        }
-        case V_MODP: {
-            const uint32_t p = md.p;
-            const uint32_t a = ((const uint32_t *)s)[e] % p;
-            const double b = a > p / 2 ? (double)a - (double)p : (double)a;
-            ((double *)d)[t] = 2.0 * b;
-            ((double *)d)[nn + t] = -2.0 * b;
-            break;
-        }
-        case V_MONT: {
-            const uint32_t p = md.p;
-            const uint32_t a = ((const uint32_t *)s)[e] % p;
-            const uint32_t two = (uint32_t)((2ull * a) % p);
-            uint32_t *o = (uint32_t *)d;
-            o[t] = two;
-            o[nn + t] = two ? p - two : 0u;
-            o[2 * nn + t] = a;
-            o[3 * nn + t] = a ? p - a : 0u;
-            break;
-        }
-        }
-    }
+    stage_one(mats[blockIdx.x], src, stage);
 }
 
 // ---------------------------------------------------------------- finalize
@@ -113,12 +62,12 @@ int walk_occupancy(int variant, int n, bool kahan, bool fused, int nmax_fused, i
 int launch_walk(int variant, int n, bool kahan, bool fused, int nmax_fused, const WaveItem *d_items,
                 uint32_t count, uint32_t grab, const MatDesc *d_mats, const void *stage,
                 double *partials, unsigned long long *ctr, CtrState *state, int grid_blocks,
-                void *stream, void *fin_out, int fin_nmats)
+                void *stream, const void *fin_src, void *fin_out, int fin_nmats)
 {
     WalkFn f = pick(variant, n, kahan, fused, nmax_fused);
     if (!f || grab < 1 || !state) return (int)hipErrorInvalidValue;
     if (grid_blocks < 1) grid_blocks = 1;
-    if (fin_nmats < 0 || (fin_nmats > 0 && (grid_blocks != 1 || !fin_out)))
+    if (fin_nmats < 0 || (fin_nmats > 0 && (grid_blocks != 1 || !fin_out || !fin_src)))
         return (int)hipErrorInvalidValue;
     const uint64_t per_run = (uint64_t)(BLOCK / WAVE) * grab;
     const uint64_t runs = ((uint64_t)count + per_run - 1) / per_run;
@@ -126,6 +75,7 @@ int launch_walk(int variant, int n, bool kahan, bool fused, int nmax_fused, cons
     ca.groups = ctr_groups(grid_blocks);
     ca.runs = (uint32_t)runs;
     ca.fin_out = (char *)fin_out;
+    ca.fin_src = (const char *)fin_src;
     ca.fin_nmats = (uint32_t)fin_nmats;
     for (int x = 0; x < CTR_GROUPS; ++x) ca.base[x] = state->base[x];
     const char *st = (const char *)stage;

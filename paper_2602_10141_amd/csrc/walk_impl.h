@@ -665,6 +665,63 @@ struct Occupancy {
                     : (N > 40 ? 3 : 4);
 };
 
+// ----------------------------------------------------------------- staging
+// Staged layout, column-major (column k, row i at k*n + i):
+//   c128, f64, F_p (Barrett): [+2A][-2A] as binary64 (complex: re, im pairs);
+//                             F_p entries are first mapped to balanced
+//                             residues in [-(p-1)/2, (p-1)/2];
+//   F_p (Montgomery):         [2a mod p][(p - 2a) mod p][a][(p - a) mod p] as uint32.
+// Entries of F_p matrices are reduced mod p first.
+__device__ inline void stage_one(const MatDesc md, const char *src, char *stage)
+{
+    const int n = md.n;
+    const int nn = n * n;
+    const char *s = src + md.src_off;
+    char *d = stage + md.stage_off;
+    for (int e = threadIdx.x; e < nn; e += blockDim.x) {
+        const int i = e / n;          // source row
+        const int k = e - i * n;      // source column
+        const int t = k * n + i;      // staged: column k, row i
+        switch (md.variant) {
+        case V_C128: {
+            const double *a = (const double *)s + 2 * (size_t)e;
+            double *o = (double *)d;
+            o[2 * t] = 2.0 * a[0];
+            o[2 * t + 1] = 2.0 * a[1];
+            o[2 * nn + 2 * t] = -2.0 * a[0];
+            o[2 * nn + 2 * t + 1] = -2.0 * a[1];
+            break;
+        }
+        case V_F64: {
+            const double a = ((const double *)s)[e];
+            ((double *)d)[t] = 2.0 * a;
+            ((double *)d)[nn + t] = -2.0 * a;
+            break;
+        }
+        case V_MODP: {
+            const uint32_t p = md.p;
+            const uint32_t a = ((const uint32_t *)s)[e] % p;
+            const double b = a > p / 2 ? (double)a - (double)p : (double)a;
+            ((double *)d)[t] = 2.0 * b;
+            ((double *)d)[nn + t] = -2.0 * b;
+            break;
+        }
+        case V_MONT: {
+            const uint32_t p = md.p;
+            const uint32_t a = ((const uint32_t *)s)[e] % p;
+            const uint32_t two = (uint32_t)((2ull * a) % p);
+            uint32_t *o = (uint32_t *)d;
+            o[t] = two;
+            o[nn + t] = two ? p - two : 0u;
+            o[2 * nn + t] = a;
+            o[3 * nn + t] = a ? p - a : 0u;
+            break;
+        }
+        }
+    }
+}
+
+
 // ---------------------------------------------------------------- finalize
 // Per matrix, with the 256 threads of a block: reduce its partial slots in a
 // fixed order (strided compensated sums, then a fixed tree), apply
@@ -813,9 +870,21 @@ __device__ __forceinline__ void for_each_run(BlockClaims &bc, int lane, F &&walk
     for (uint32_t r = blockIdx.x; r < bc.runs; r = claims ? bc.next(lane) : bc.runs) walk_run(r);
 }
 
-// A launch of one block finalizes its own matrices (after every wave's
-// partials are stored), saving the finalize launch for a single small
-// matrix.
+// A launch that is the whole call in one block (a single small matrix, or a
+// few tiny ones) stages its matrices itself before walking and finalizes
+// them afterwards, saving two launches.  The block's vector stores complete
+// before the barrier; the scalar cache starts every dispatch empty and no
+// scalar load touches the staged lines before they are written, so the
+// walk's column loads read the new values (from this XCD's L2).
+__device__ __forceinline__ void stage_in_walk(const CtrArgs &ca, const MatDesc *mats,
+                                              const char *stage)
+{
+    if (!ca.fin_nmats) return;
+    for (uint32_t m = 0; m < ca.fin_nmats; ++m)
+        stage_one(mats[m], ca.fin_src, const_cast<char *>(stage));
+    __syncthreads();
+}
+
 __device__ __forceinline__ void finalize_in_walk(const CtrArgs &ca, const MatDesc *mats,
                                                  const double *partials)
 {
@@ -840,6 +909,8 @@ void walk_kernel(const WaveItem *items, uint32_t count, uint32_t grab,
 {
     __shared__ uint32_t slot[2];
     const int lane = threadIdx.x & (WAVE - 1);
+    stage_in_walk(ca, mats, stage);
+    stage = opaque(stage);              // no column load moves above the staging
     BlockClaims bc = block_claims(ctr, ca, slot);
     const uint32_t per_run = WPB * grab;
     for_each_run(bc, lane, [&](uint32_t r) __attribute__((always_inline)) {
@@ -883,6 +954,8 @@ void walk_fused(const WaveItem *items, uint32_t count, uint32_t grab,
 {
     __shared__ uint32_t slot[2];
     const int lane = threadIdx.x & (WAVE - 1);
+    stage_in_walk(ca, mats, stage);
+    stage = opaque(stage);              // no column load moves above the staging
     BlockClaims bc = block_claims(ctr, ca, slot);
     const uint32_t per_run = WPB * grab;
     for_each_run(bc, lane, [&](uint32_t r) __attribute__((always_inline)) {

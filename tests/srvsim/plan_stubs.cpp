@@ -7,7 +7,7 @@ namespace permk {
 int launch_stage(const MatDesc *, int, const void *, void *, void *) { return 0; }
 int launch_walk(int, int, bool, bool, int, const WaveItem *, uint32_t, uint32_t,
                 const MatDesc *, const void *, double *, unsigned long long *, CtrState *, int,
-                void *, void *, int)
+                void *, const void *, void *, int)
 {
     return 0;
 }

@@ -59,9 +59,10 @@ int launch_stage(const MatDesc *d_mats, int nmats, const void *src, void *stage,
 int launch_walk(int, int, bool, bool, int, const WaveItem *d_items, uint32_t count,
                 uint32_t grab, const MatDesc *d_mats, const void *stage, double *partials,
                 unsigned long long *ctr, CtrState *state, int grid_blocks, void *stream,
-                void *fin_out, int fin_nmats)
+                const void *fin_src, void *fin_out, int fin_nmats)
 {
-    if (fin_nmats) return 1;      // the request loop always finalizes separately
+    if (fin_nmats) return 1;      // the request loop always stages and finalizes separately
+    (void)fin_src;
     (void)fin_out;
     if (grab < 1 || !state) return 1;
     if (grid_blocks < 1) grid_blocks = 1;
