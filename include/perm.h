@@ -143,9 +143,14 @@ int perm_range(perm_ctx *ctx, const perm_item *item, const void *data, uint64_t 
                void *out16, unsigned flags, void *stream);
 
 /* Walk-kernel timing.  While enabled, the context records a pair of HIP
- * events around every walk-kernel launch, on the stream the kernel runs on.
- * perm_prof_read waits for the recorded launches, returns their summed
- * device time in milliseconds and their count, and clears the record. */
+ * events around every walk-kernel launch, on the stream the kernel runs on
+ * (a launch of one block that stages and finalizes its call's matrices
+ * includes that work).  Enabling creates events for 256 launches up front;
+ * recording a pair still adds about 9 us to a call's turnaround on the
+ * stream, so time small calls' throughput with timing off.  perm_prof_read waits for the
+ * recorded launches, returns their summed device time in milliseconds and
+ * their count, and clears the record.  Errors: PERM_EINVAL (NULL),
+ * PERM_EDEVICE (event creation or timing failed). */
 int perm_prof_enable(perm_ctx *ctx, int on);
 int perm_prof_read(perm_ctx *ctx, double *walk_ms, uint64_t *launches);
 

@@ -853,6 +853,20 @@ extern "C" int perm_crt_int(perm_ctx *ctx, const uint32_t *mats, const uint32_t 
 extern "C" int perm_prof_enable(perm_ctx *ctx, int on)
 {
     if (!ctx) return fail(PERM_EINVAL, "ctx is NULL");
+    if (on) {
+        // event pairs for the next 256 launches, created here rather than
+        // inside timed calls
+        HIPCHK(hipSetDevice(ctx->device));
+        while (ctx->prof_pool.size() + ctx->prof_pending.size() < 256) {
+            std::pair<hipEvent_t, hipEvent_t> ev{nullptr, nullptr};
+            HIPCHK(hipEventCreate(&ev.first));
+            if (hipEventCreate(&ev.second) != hipSuccess) {
+                hipEventDestroy(ev.first);
+                return fail(PERM_EDEVICE, "hipEventCreate failed");
+            }
+            ctx->prof_pool.push_back(ev);
+        }
+    }
     ctx->prof_on = on != 0;
     return PERM_OK;
 }
