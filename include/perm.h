@@ -23,7 +23,9 @@
  *   which case matrices and outputs named "dev-or-host" are device pointers
  *   (e.g. torch tensor data_ptr()) and the call is asynchronous on `stream`
  *   except where noted.  `stream` is a hipStream_t or NULL for the context's
- *   own stream.
+ *   own stream.  A single-matrix call's device output aligned to its element
+ *   type is written by the kernels directly (exactly its bytes), otherwise
+ *   through a device copy.
  * - The caller owns every buffer it passes.  The context owns only its
  *   device scratch (staged matrices, partial sums, plans), which grows on
  *   demand up to the context's HBM budget and is reused across calls.

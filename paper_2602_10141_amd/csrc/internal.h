@@ -29,6 +29,7 @@ struct MatIn {
     bool full = true;          // whole range [0, 2^(n-1))
     uint64_t x0 = 0, x1 = 0;   // else this range
     bool no_scale = false;     // leave the Glynn sum unscaled
+    int out_bytes = 16;        // bytes of the result slot written (16, 8 or 4)
 };
 
 // One walk launch.

@@ -22,6 +22,8 @@ constexpr int BLOCK = 256;      // threads per block of the walk kernels (4 wave
 // MatDesc.flags
 constexpr uint32_t MD_KAHAN    = 1u;   // compensated summation (floats)
 constexpr uint32_t MD_NO_SCALE = 2u;   // finalize leaves the Glynn sum unscaled (range partials)
+constexpr uint32_t MD_OUT_8    = 4u;   // finalize writes only the first 8 bytes of the slot (f64)
+constexpr uint32_t MD_OUT_4    = 8u;   // ... only the first 4 bytes (F_p residue)
 
 // One matrix of a launch.  64 bytes, read with scalar loads.
 struct MatDesc {

@@ -195,7 +195,7 @@ static bool same_input(const MatIn &a, const MatIn &b)
 {
     return a.variant == b.variant && a.n == b.n && a.p == b.p && a.src_off == b.src_off &&
            a.out_slot == b.out_slot && a.kahan == b.kahan && a.full == b.full && a.x0 == b.x0 &&
-           a.x1 == b.x1 && a.no_scale == b.no_scale;
+           a.x1 == b.x1 && a.no_scale == b.no_scale && a.out_bytes == b.out_bytes;
 }
 
 // Plans of at most this many matrices are cached (repeated small calls such
@@ -295,7 +295,8 @@ int plan(perm_ctx *ctx, const std::vector<MatIn> &in, Plan &pl)
         d.n = a.n;
         d.variant = a.variant;
         d.p = a.p;
-        d.flags = (a.kahan ? MD_KAHAN : 0) | (a.no_scale ? MD_NO_SCALE : 0);
+        d.flags = (a.kahan ? MD_KAHAN : 0) | (a.no_scale ? MD_NO_SCALE : 0) |
+                  (a.out_bytes == 8 ? MD_OUT_8 : 0) | (a.out_bytes == 4 ? MD_OUT_4 : 0);
         d.pinv = a.p ? 1.0 / (double)a.p : 0.0;
         d.mont_pp = (a.variant == V_MONT) ? permh::mont_pprime(a.p) : 0;
         d.out_slot = a.out_slot;
@@ -617,8 +618,18 @@ static int single(perm_ctx *ctx, int variant, const void *A, int n, uint32_t p, 
     in[0].p = p;
     in[0].kahan = !(flags & PERM_NO_KAHAN);
     in[0].full = true;
+    // A device output with the alignment of its element type receives the
+    // result straight from the finalize step (only out_bytes written), with
+    // no copy launch; otherwise the 16-byte slot goes through ctx->outs.
+    const bool direct = (flags & PERM_DEVICE_PTRS) &&
+                        (uintptr_t)out % (out_bytes >= 8 ? 8 : 4) == 0;
+    in[0].out_bytes = direct ? (int)out_bytes : 16;
     Plan &pl = ctx->scratch_plan;
     if ((rc = plan(ctx, in, pl)) != PERM_OK) return rc;
+    if (direct) {
+        if ((rc = execute(ctx, pl, src, out, 1, s)) != PERM_OK) return rc;
+        return end_call(ctx, s);
+    }
     if ((rc = ensure(ctx, ctx->outs, 256)) != PERM_OK) return rc;
     if ((rc = execute(ctx, pl, src, ctx->outs.p, 1, s)) != PERM_OK) return rc;
     if (flags & PERM_DEVICE_PTRS) {

@@ -726,7 +726,8 @@ __device__ inline void stage_one(const MatDesc md, const char *src, char *stage)
 // Per matrix, with the 256 threads of a block: reduce its partial slots in a
 // fixed order (strided compensated sums, then a fixed tree), apply
 // 2^{-(n-1)} (floats) or inv(2)^{n-1} (F_p; Montgomery's R^{-(n-1)} too),
-// write the 16-byte result slot.  Shared by finalize_kernel and by walk
+// write the 16-byte result slot (only its first 8 or 4 bytes with MD_OUT_8
+// or MD_OUT_4: a caller's f64 or F_p output written in place).  Shared by finalize_kernel and by walk
 // launches of one block, which finalize their own matrices, so the two give
 // identical bits.  sa, sb, su: 256 entries each in LDS.
 __device__ inline uint64_t powmod_u64(uint64_t b, uint32_t e, uint64_t p)
@@ -753,10 +754,11 @@ __device__ inline void finalize_one(const MatDesc md, const double *partials, ch
         if (t == 0) {
             if (modp) {
                 ((uint32_t *)o)[0] = 1u % md.p;
-                ((uint32_t *)o)[1] = ((uint32_t *)o)[2] = ((uint32_t *)o)[3] = 0u;
+                if (!(md.flags & MD_OUT_4))
+                    ((uint32_t *)o)[1] = ((uint32_t *)o)[2] = ((uint32_t *)o)[3] = 0u;
             } else {
                 ((double *)o)[0] = 1.0;
-                ((double *)o)[1] = 0.0;
+                if (!(md.flags & MD_OUT_8)) ((double *)o)[1] = 0.0;
             }
         }
         return;
@@ -782,7 +784,8 @@ __device__ inline void finalize_one(const MatDesc md, const double *partials, ch
             if (!(md.flags & MD_NO_SCALE)) f = (f * powmod_u64((P + 1) / 2, md.n - 1, P)) % P;
             v = (v * f) % P;
             ((uint32_t *)o)[0] = (uint32_t)v;
-            ((uint32_t *)o)[1] = ((uint32_t *)o)[2] = ((uint32_t *)o)[3] = 0u;
+            if (!(md.flags & MD_OUT_4))
+                ((uint32_t *)o)[1] = ((uint32_t *)o)[2] = ((uint32_t *)o)[3] = 0u;
         }
         return;
     }
@@ -807,7 +810,7 @@ __device__ inline void finalize_one(const MatDesc md, const double *partials, ch
             b = __builtin_ldexp(b, -(md.n - 1));
         }
         ((double *)o)[0] = a;
-        ((double *)o)[1] = md.variant == V_C128 ? b : 0.0;
+        if (!(md.flags & MD_OUT_8)) ((double *)o)[1] = md.variant == V_C128 ? b : 0.0;
     }
 }
 

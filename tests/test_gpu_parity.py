@@ -97,6 +97,48 @@ def test_device_pointer_path(P, ctx, O):
     assert int(o.cpu()[0]) == O.native.ryser_modp(R, 1073742209)
 
 
+def test_device_outputs_written_in_place(P, ctx, O):
+    """A single-matrix device output aligned to its element type is written
+    by the kernels directly: exactly 16, 8 or 4 bytes, with the neighbouring
+    bytes untouched.  An f64 output 4 bytes off its alignment goes through
+    the copy path and holds the same value."""
+    import ctypes
+    import torch
+    L, st = P.lib(), P._stream(None)
+    g = E.rng(5, 2)
+    A = E.ginibre_complex(12, g)
+    B = E.ginibre_real(11, g)
+    R = E.random_residues(10, 65537, g)
+    dA = torch.from_numpy(A).cuda()
+    dB = torch.from_numpy(B).cuda()
+    dR = torch.from_numpy(R.astype(np.int32)).cuda()
+    buf = torch.full((8,), -7.0, dtype=torch.float64, device="cuda")
+    base = buf.data_ptr()
+    assert L.perm_c128(ctx.ptr, ctypes.c_void_p(dA.data_ptr()), 12, ctypes.c_void_p(base + 16),
+                       P.PERM_DEVICE_PTRS, st) == P.PERM_OK
+    assert L.perm_f64(ctx.ptr, ctypes.c_void_p(dB.data_ptr()), 11, ctypes.c_void_p(base + 40),
+                      P.PERM_DEVICE_PTRS, st) == P.PERM_OK
+    torch.cuda.synchronize()
+    h = buf.cpu().numpy()
+    assert list(h[[0, 1, 4, 6, 7]]) == [-7.0] * 5
+    assert abs(complex(h[2], h[3]) - O.native.ryser_c128(A)) <= TOL * scale(A)
+    assert abs(h[5] - O.native.ryser_f64(B)) <= TOL * scale(B)
+    ibuf = torch.full((8,), -1, dtype=torch.int32, device="cuda")
+    assert L.perm_modp(ctx.ptr, ctypes.c_void_p(dR.data_ptr()), 10, 65537,
+                       ctypes.c_void_p(ibuf.data_ptr() + 12), P.PERM_DEVICE_PTRS, st) == P.PERM_OK
+    torch.cuda.synchronize()
+    hi = ibuf.cpu().numpy()
+    assert hi[3] == O.native.ryser_modp(R, 65537)
+    assert list(np.delete(hi, 3)) == [-1] * 7
+    # misaligned f64 output: copied, same bits as the aligned result
+    raw = torch.zeros(32, dtype=torch.uint8, device="cuda")
+    assert L.perm_f64(ctx.ptr, ctypes.c_void_p(dB.data_ptr()), 11, ctypes.c_void_p(raw.data_ptr() + 4),
+                      P.PERM_DEVICE_PTRS, st) == P.PERM_OK
+    torch.cuda.synchronize()
+    got = np.frombuffer(raw.cpu().numpy()[4:12].tobytes(), dtype=np.float64)[0]
+    assert got == h[5]
+
+
 def test_kahan_off_still_within_tolerance(P, ctx, O):
     A = E.ginibre_complex(16, E.rng(6, 0))
     got = P.perm_c128(ctx, A, flags=P.PERM_NO_KAHAN)
