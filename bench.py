@@ -595,6 +595,54 @@ def bench_stats(P, ctx, args):
             "runs": runs}
 
 
+def bench_sizes(P, ctx, args):
+    """One matrix per call across the orders of the headline metric: Haar
+    U(n) (c128) and O(n) (f64) for n = 20..36 and the Schur matrix S_n mod
+    one prime (F_p) for n = 28..36.  Per case: the call's time and terms/s
+    and the walk kernel's fraction of the FP64 VALU peak.  The chunk length
+    is the library default, i.e. the partition batches use, so a single
+    matrix of order 24..28 occupies only part of the device."""
+    import torch
+    from paper_2602_10141_amd import ensembles as E
+    cases = ([("c128", n) for n in (20, 24, 28, 30, 32, 34, 36)] +
+             [("f64", n) for n in (20, 24, 28, 32, 36)] +
+             [("modp", n) for n in (28, 30, 32, 34, 36)])
+    rows, tot_terms, tot_s = [], 0, 0.0
+    for field, n in cases:
+        if field == "c128":
+            A = torch.from_numpy(E.haar_unitary(n, E.rng(50, n))).cuda()
+            fn = lambda: P.perm_c128(ctx, A)
+        elif field == "f64":
+            A = torch.from_numpy(E.haar_orthogonal(n, E.rng(51, n))).cuda()
+            fn = lambda: P.perm_f64(ctx, A)
+        else:
+            p = P.perm_schur_primes(n)[0]
+            A = torch.from_numpy(P.perm_schur_residues(n, p).astype(np.int32)).cuda()
+            fn = lambda: P.perm_modp(ctx, A, p)
+        terms = 1 << (n - 1)
+        reps = max(1, int(4e9 / terms))
+        fn()
+        sync()
+        P.perm_prof_enable(ctx, True)
+        P.perm_prof_read(ctx)
+        t0 = time.perf_counter()
+        for _ in range(reps):
+            fn()
+        sync()
+        dt = (time.perf_counter() - t0) / reps
+        walk_ms, launches = P.perm_prof_read(ctx)
+        P.perm_prof_enable(ctx, False)
+        rows.append({"field": field, "n": n, "ms": dt * 1e3, "terms_per_s": terms / dt,
+                     "roofline": roofline(terms * ops_per_term(field, n), walk_ms, launches)})
+        tot_terms += terms
+        tot_s += dt
+    return {"metric": METRIC, "value": tot_terms / tot_s, "unit": "subset-terms/s",
+            "ms_per_step": tot_s * 1e3, "dtype": "f64",
+            "config": {"workload": "single_matrix_orders_20_36",
+                       "cases": [f"{f}{n}" for f, n in cases]},
+            "runs": rows}
+
+
 def bench_dft(P, ctx, args):
     """The DFT-geodesic fingerprint (paper Sec. 4.3): perm(gamma(t)) on a
     257-point t grid for odd n in 7..23 and both logarithms of -1, one
@@ -684,7 +732,7 @@ def bench_schur_odd(P, ctx, args):
 
 
 WORKLOADS = {"dft": bench_dft, "stats": bench_stats, "schur_odd": bench_schur_odd, "copycal": bench_copycal, "serve": bench_serve, "schur28": bench_schur, "single14": bench_single14, "haar20": bench_haar20,
-             "ragged": bench_ragged}
+             "ragged": bench_ragged, "sizes": bench_sizes}
 
 
 def main():
