@@ -200,13 +200,14 @@ struct RealRows {
 
 // ------------------------------------------------------------------- C128
 // Prefetched column entries per variant, from same-device comparisons: the
-// pipelined walk is faster for c128 when the whole column fits (n <= 20) and
-// for F_p; a partial c128 column (n >= 21) and the f64 walk, whose VGPR
-// budget at its occupancy leaves no room for the earlier loads, run faster
-// without it.
+// pipelined walk is faster for F_p and for c128, with the whole column up
+// to n = 20, its first 32 entries for n = 21..26 (2% faster at n = 23, 26
+// than no prefetch; 40 entries were slower there) and 40 entries beyond
+// (0-2% faster); the f64 walk, whose VGPR budget at its occupancy leaves no
+// room for the earlier loads, was not faster with it.
 template <int N>
 struct PfC128 {
-    static constexpr int n = 2 * N <= PF_MAX ? 2 * N : 0;
+    static constexpr int n = 2 * N <= PF_MAX ? 2 * N : (N <= 26 ? 32 : PF_MAX);
 };
 
 template <int N, bool KAHAN>
