@@ -282,9 +282,9 @@ struct OpsC128 : RealRows<N, 2, PfC128<N>::n> {
 };
 
 // -------------------------------------------------------------------- F64
-template <int N, bool KAHAN>
-struct OpsF64 : RealRows<N, 1, 0> {
-    using RealRows<N, 1, 0>::r;
+template <int N, bool KAHAN, int PFN = 0>
+struct OpsF64 : RealRows<N, 1, PFN> {
+    using RealRows<N, 1, PFN>::r;
     double s, c;
     double g, h;                // the running group of four terms
 
@@ -935,7 +935,8 @@ __device__ __forceinline__ void run_variant(int v, const WaveItem &it, const Mat
                                             const char *stage, double *partials, int lane)
 {
     if (v == V_C128) run_item<OpsC128<N, KAHAN>>(it, md, stage, partials, lane);
-    else if (v == V_F64) run_item<OpsF64<N, KAHAN>>(it, md, stage, partials, lane);
+    else if (v == V_F64)    // at the fused kernel's 3 waves f64 has registers for the prefetch
+        run_item<OpsF64<N, KAHAN, (N < PF_MAX ? N : PF_MAX)>>(it, md, stage, partials, lane);
     else run_item<OpsModp<N>>(it, md, stage, partials, lane);
 }
 
