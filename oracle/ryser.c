@@ -42,7 +42,7 @@
 #include <stdint.h>
 #include <stddef.h>
 
-#define ORACLE_NMAX 40
+#define ORACLE_NMAX 48            /* the largest order the library accepts */
 
 static unsigned ctz64(uint64_t x) {
     unsigned k = 0;

@@ -215,6 +215,36 @@ def test_range_partials(P, ctx, O, field):
             assert got == O.native.glynn_range_modp(A, 1073742209, x0, x1)
 
 
+@pytest.mark.parametrize("field,n", [("c128", 40), ("c128", 48), ("f64", 48), ("modp", 44),
+                                     ("modp", 48)])
+def test_range_partials_large_orders(P, ctx, O, field, n):
+    """Orders up to the maximum, 48, through Gray-index windows the oracle can
+    afford (its Glynn terms cost O(n^2) each): at the start, around the
+    middle, at the end of [0, 2^(n-1)) and at an unaligned offset past 2^33,
+    each spanning several wave items of the large-order kernels."""
+    T = 1 << (n - 1)
+    g = E.rng(8, n)
+    p = 1073742209
+    if field == "c128":
+        A = E.ginibre_complex(n, g)
+    elif field == "f64":
+        A = E.ginibre_real(n, g)
+    else:
+        A = E.random_residues(n, p, g)
+    items, data = P.pack_matrices([(A, field, p if field == "modp" else 0)])
+    for x0, x1 in [(0, 1 << 14), (T // 2 - 3000, T // 2 + 9000), (T - 20000, T),
+                   ((1 << 33) + 5, (1 << 33) + 4101)]:
+        got = P.perm_range(ctx, items[0], data, x0, x1)
+        if field == "c128":
+            want = O.native.glynn_range_c128(A, x0, x1)
+            assert abs(got - want) <= TOL * scale(A) * (x1 - x0) ** 0.5
+        elif field == "f64":
+            want = O.native.glynn_range_f64(A, x0, x1)
+            assert abs(got - want) <= TOL * scale(A) * (x1 - x0) ** 0.5
+        else:
+            assert got == O.native.glynn_range_modp(A, p, x0, x1)
+
+
 def test_range_rejects_bad_bounds(P, ctx):
     items, data = P.pack_matrices([(np.eye(5), "f64", 0)])
     with pytest.raises(P.PermError) as e:
