@@ -191,7 +191,7 @@ def test_crt_factorial_sign(P, ctx, O):
 
 
 # ------------------------------------------------------------------- ranges
-@pytest.mark.parametrize("field", ["c128", "f64", "modp"])
+@pytest.mark.parametrize("field", ["c128", "f64", "modp", "mont"])
 def test_range_partials(P, ctx, O, field):
     n = 14
     T = 1 << (n - 1)
@@ -202,9 +202,11 @@ def test_range_partials(P, ctx, O, field):
         A = E.ginibre_real(n, g)
     else:
         A = E.random_residues(n, 1073742209, g)
-    items, data = P.pack_matrices([(A, field, 1073742209 if field == "modp" else 0)])
+    modp = field in ("modp", "mont")
+    items, data = P.pack_matrices([(A, "modp" if modp else field, 1073742209 if modp else 0)])
+    flags = P.PERM_MONTGOMERY if field == "mont" else 0
     for x0, x1 in [(0, T), (1, 2), (3, 77), (100, 4100), (T - 5, T), (0, 1), (4096, 8192), (7, 7)]:
-        got = P.perm_range(ctx, items[0], data, x0, x1)
+        got = P.perm_range(ctx, items[0], data, x0, x1, flags=flags)
         if field == "c128":
             want = O.native.glynn_range_c128(A, x0, x1)
             assert abs(got - want) <= TOL * scale(A) * max(1, x1 - x0) ** 0.5
@@ -216,7 +218,7 @@ def test_range_partials(P, ctx, O, field):
 
 
 @pytest.mark.parametrize("field,n", [("c128", 40), ("c128", 48), ("f64", 48), ("modp", 44),
-                                     ("modp", 48)])
+                                     ("modp", 48), ("mont", 41), ("mont", 48)])
 def test_range_partials_large_orders(P, ctx, O, field, n):
     """Orders up to the maximum, 48, through Gray-index windows the oracle can
     afford (its Glynn terms cost O(n^2) each): at the start, around the
@@ -231,10 +233,12 @@ def test_range_partials_large_orders(P, ctx, O, field, n):
         A = E.ginibre_real(n, g)
     else:
         A = E.random_residues(n, p, g)
-    items, data = P.pack_matrices([(A, field, p if field == "modp" else 0)])
+    modp = field in ("modp", "mont")
+    items, data = P.pack_matrices([(A, "modp" if modp else field, p if modp else 0)])
+    flags = P.PERM_MONTGOMERY if field == "mont" else 0
     for x0, x1 in [(0, 1 << 14), (T // 2 - 3000, T // 2 + 9000), (T - 20000, T),
                    ((1 << 33) + 5, (1 << 33) + 4101)]:
-        got = P.perm_range(ctx, items[0], data, x0, x1)
+        got = P.perm_range(ctx, items[0], data, x0, x1, flags=flags)
         if field == "c128":
             want = O.native.glynn_range_c128(A, x0, x1)
             assert abs(got - want) <= TOL * scale(A) * (x1 - x0) ** 0.5
