@@ -199,15 +199,21 @@ struct RealRows {
 };
 
 // ------------------------------------------------------------------- C128
-// Prefetched column entries per variant, from same-device comparisons: the
-// pipelined walk is faster for F_p and for c128, with the whole column up
-// to n = 20, its first 32 entries for n = 21..26 (2% faster at n = 23, 26
-// than no prefetch; 40 entries were slower there) and 40 entries beyond
-// (0-2% faster); the f64 walk, whose VGPR budget at its occupancy leaves no
-// room for the earlier loads, was not faster with it.
+// Prefetched column entries per variant.  F_p and c128 up to n = 20 (the
+// whole column) were faster in same-device comparisons.  For c128 from
+// n = 21 only part of the column fits; the depth per order is the deepest of
+// 16, 24, 32, 40 entries whose walk loop the compiler keeps free of spills
+// (the allocation changes erratically with the depth: 40 entries spilled at
+// n = 22..28, 32 at n = 24, 25, 27, 28), with the fewest waits per group.
+// The f64 walk, whose VGPR budget at its occupancy leaves no room for the
+// earlier loads, was not faster with it.
 template <int N>
 struct PfC128 {
-    static constexpr int n = 2 * N <= PF_MAX ? 2 * N : (N <= 26 ? 32 : PF_MAX);
+    static constexpr int n = 2 * N <= PF_MAX ? 2 * N
+                           : N == 21 ? 40
+                           : (N <= 23 || N == 26) ? 32
+                           : N <= 28 ? 16
+                           : PF_MAX;
 };
 
 template <int N, bool KAHAN>
