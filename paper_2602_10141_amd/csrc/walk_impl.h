@@ -204,7 +204,8 @@ struct RealRows {
 // n = 21 only part of the column fits; the depth per order is the deepest of
 // 16, 24, 32, 40 entries whose walk loop the compiler keeps free of spills
 // (the allocation changes erratically with the depth: 40 entries spilled at
-// n = 22..28, 32 at n = 24, 25, 27, 28), with the fewest waits per group.
+// n = 22..28 and at most orders from 32, 32 at n = 24, 25, 27, 28), with the
+// fewest waits per group; 16 is spill-free at every order from 21.
 // The f64 walk, whose VGPR budget at its occupancy leaves no room for the
 // earlier loads, was not faster with it.
 template <int N>
@@ -213,7 +214,8 @@ struct PfC128 {
                            : N == 21 ? 40
                            : (N <= 23 || N == 26) ? 32
                            : N <= 28 ? 16
-                           : PF_MAX;
+                           : N <= 31 ? PF_MAX
+                           : 16;
 };
 
 template <int N, bool KAHAN>
