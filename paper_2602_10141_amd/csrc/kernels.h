@@ -106,9 +106,11 @@ int launch_stage(const MatDesc *d_mats, int nmats, const void *src, void *stage,
 // bytes apart.  Block b claims runs of items from counter b mod `groups`
 // (groups = the largest power of two <= min(8, grid), so that the remainder
 // is a scalar AND); workgroups are dispatched round-robin over the XCDs, so
-// each counter serves the blocks of one XCD.  Counter x serves the runs
-// r = x, x + groups, x + 2 groups, ... (striding keeps the largest-first
-// order balanced across XCDs).  The host tracks each counter's value.
+// each counter serves the blocks of one XCD.  Block b walks run b without a
+// claim; counter x then hands out the runs x + groups * (nb + k), k = 0, 1,
+// ..., nb being the number of blocks of group x (striding keeps the
+// largest-first order balanced across XCDs).  The host tracks each
+// counter's value.
 constexpr int CTR_GROUPS = 8;
 constexpr int CTR_STRIDE = 32;                                  // in uint64
 constexpr size_t CTR_BYTES = (size_t)CTR_GROUPS * CTR_STRIDE * 8;
