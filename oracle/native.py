@@ -4,6 +4,7 @@ Every function takes a numpy array holding one n x n matrix in row-major
 order (complex128, float64 or uint32 residues) and returns a Python scalar.
 The library is built on first use if it is missing.
 """
+import concurrent.futures as cf
 import ctypes
 import os
 
@@ -29,6 +30,7 @@ def lib():
             ("oracle_ryser_f64", [dp, c_int, c_int, dp]),
             ("oracle_ryser_modp", [u32p, c_int, c_u32, u32p]),
             ("oracle_ryser_modp_prefix", [u32p, c_int, c_u32, u64, u32p]),
+            ("oracle_ryser_modp_range", [u32p, c_int, c_u32, u64, u64, u32p]),
             ("oracle_glynn_range_c128", [dp, c_int, u64, u64, dp]),
             ("oracle_glynn_range_f64", [dp, c_int, u64, u64, dp]),
             ("oracle_glynn_range_modp", [u32p, c_int, c_u32, u64, u64, u32p]),
@@ -92,6 +94,52 @@ def ryser_modp_prefix(A, p: int, x_end: int) -> int:
     out = np.zeros(1, dtype=np.uint32)
     _check(lib().oracle_ryser_modp_prefix(A.ctypes.data, n, int(p), x_end, out.ctypes.data))
     return int(out[0])
+
+
+def ryser_modp_range(A, p: int, x0: int, x1: int) -> int:
+    """Signed Ryser sum mod p over the Gray-ordered subsets x in [x0, x1),
+    1 <= x0 <= x1 <= 2^n, without the final (-1)^n."""
+    A, n = _mat(A, np.uint32)
+    out = np.zeros(1, dtype=np.uint32)
+    _check(lib().oracle_ryser_modp_range(A.ctypes.data, n, int(p), x0, x1, out.ctypes.data))
+    return int(out[0])
+
+
+def _spans(x0, x1, parts):
+    """[x0, x1) cut into at most `parts` contiguous pieces."""
+    parts = max(1, min(parts, x1 - x0))
+    cuts = [x0 + (x1 - x0) * i // parts for i in range(parts + 1)]
+    return [(a, b) for a, b in zip(cuts, cuts[1:]) if a < b]
+
+
+def default_threads() -> int:
+    return min(16, os.cpu_count() or 1)
+
+
+def ryser_modp_threaded(A, p: int, threads: int = None) -> int:
+    """perm(A) mod p by Ryser's formula, the subset range [1, 2^n) split into
+    contiguous pieces summed on host threads (the C calls release the GIL)."""
+    A, n = _mat(A, np.uint32)
+    if n == 0:
+        return 1 % p
+    threads = threads or default_threads()
+    with cf.ThreadPoolExecutor(threads) as ex:
+        parts = list(ex.map(lambda s: ryser_modp_range(A, p, *s), _spans(1, 1 << n, 4 * threads)))
+    tot = sum(parts) % p
+    return (p - tot) % p if n % 2 else tot
+
+
+def glynn_range_threaded(A, x0: int, x1: int, field: str, p: int = 0, threads: int = None):
+    """glynn_range_{c128,f64,modp} over [x0, x1) split into pieces on host
+    threads; the pieces' sums are added (mod p for F_p)."""
+    threads = threads or default_threads()
+    fn = {"c128": lambda s: glynn_range_c128(A, *s), "f64": lambda s: glynn_range_f64(A, *s),
+          "modp": lambda s: glynn_range_modp(A, p, *s)}[field]
+    with cf.ThreadPoolExecutor(threads) as ex:
+        parts = list(ex.map(fn, _spans(x0, x1, 4 * threads)))
+    if field == "modp":
+        return sum(parts) % p
+    return sum(parts) if parts else 0.0
 
 
 def glynn_range_c128(A, x0: int, x1: int) -> complex:

@@ -149,15 +149,23 @@ int oracle_ryser_f64(const double *A, int n, int kahan, double *out)
 }
 
 /* ----------------------------------------------------------------- F_p */
-/* Signed Ryser sum over the Gray-ordered subsets x = 1 .. x_end-1, mod p
- * (without the final (-1)^n).  x_end = 2^n gives the whole sum. */
-static int ryser_modp_upto(const uint32_t *A, int n, uint32_t p, uint64_t x_end, uint64_t *tot_out)
+/* Signed Ryser sum over the Gray-ordered subsets x = x_begin .. x_end-1
+ * (x_begin >= 1), mod p, without the final (-1)^n.  The row sums start as
+ * those of the subset gray(x_begin - 1), added up column by column; from
+ * there the walk is the same as for the whole sum.  [1, 2^n) is the whole
+ * sum. */
+static int ryser_modp_span(const uint32_t *A, int n, uint32_t p, uint64_t x_begin, uint64_t x_end,
+                           uint64_t *tot_out)
 {
     const uint64_t P = p;
     uint64_t s[ORACLE_NMAX];
     for (int i = 0; i < n; ++i) s[i] = 0;
+    const uint64_t g0 = (x_begin - 1) ^ ((x_begin - 1) >> 1);
+    for (int j = 0; j < n; ++j)
+        if ((g0 >> j) & 1u)
+            for (int i = 0; i < n; ++i) s[i] = (s[i] + A[(size_t)i * n + j]) % P;
     uint64_t tot = 0;
-    for (uint64_t x = 1; x < x_end; ++x) {
+    for (uint64_t x = x_begin; x < x_end; ++x) {
         unsigned j = ctz64(x);
         uint64_t g = x ^ (x >> 1);
         int enters = (int)((g >> j) & 1u);
@@ -173,6 +181,11 @@ static int ryser_modp_upto(const uint32_t *A, int n, uint32_t p, uint64_t x_end,
     }
     *tot_out = tot;
     return 0;
+}
+
+static int ryser_modp_upto(const uint32_t *A, int n, uint32_t p, uint64_t x_end, uint64_t *tot_out)
+{
+    return ryser_modp_span(A, n, p, 1, x_end, tot_out);
 }
 
 int oracle_ryser_modp(const uint32_t *A, int n, uint32_t p, uint32_t *out)
@@ -196,6 +209,22 @@ int oracle_ryser_modp_prefix(const uint32_t *A, int n, uint32_t p, uint64_t x_en
     for (int i = 0; i < n * n; ++i) if (A[i] >= p) return -1;
     uint64_t tot = 0;
     ryser_modp_upto(A, n, p, x_end, &tot);
+    out[0] = (uint32_t)tot;
+    return 0;
+}
+
+/* The signed Ryser sum over the subsets x in [x_begin, x_end) of the walk
+ * above (1 <= x_begin <= x_end <= 2^n), mod p, without the final (-1)^n:
+ * disjoint ranges that cover [1, 2^n) add up to the whole sum, so one
+ * permanent can be split over host threads. */
+int oracle_ryser_modp_range(const uint32_t *A, int n, uint32_t p, uint64_t x_begin, uint64_t x_end,
+                            uint32_t *out)
+{
+    if (n < 1 || n > ORACLE_NMAX || !out || p < 2 || !A) return -1;
+    if (x_begin < 1 || x_begin > x_end || (n < 64 && x_end > ((uint64_t)1 << n))) return -1;
+    for (int i = 0; i < n * n; ++i) if (A[i] >= p) return -1;
+    uint64_t tot = 0;
+    ryser_modp_span(A, n, p, x_begin, x_end, &tot);
     out[0] = (uint32_t)tot;
     return 0;
 }

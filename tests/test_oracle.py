@@ -286,12 +286,56 @@ def test_schur_galois_invariance(O):
                 assert O.native.ryser_modp(O.crt.schur_residues(n, p, pow(g, a, p)), p) == base
 
 
-@pytest.mark.parametrize("n", [6, 8, 12, 28])
+@pytest.mark.parametrize("n", [6, 8, 12])
 def test_schur_even_n_is_zero_mod_p(O, n):
-    if n > 16:
-        pytest.skip("2^28-subset oracle run is covered by the GPU parity tests")
     for p in O.crt.primes_1_mod_n(n, 3):
         assert O.native.ryser_modp(O.crt.schur_residues(n, p), p) == 0
+
+
+def test_schur_28_is_zero_mod_first_prime(O):
+    """The benchmark's order: the full 2^28-subset Ryser sum of S_28 mod its
+    smallest prime, split over host threads, is 0 (even n)."""
+    p = O.crt.primes_1_mod_n(28, 1)[0]
+    assert O.native.ryser_modp_threaded(O.crt.schur_residues(28, p), p) == 0
+
+
+@pytest.mark.parametrize("n", [1, 2, 3, 5, 7])
+def test_ryser_modp_ranges_add_up_to_bruteforce(O, n):
+    """Random partitions of the subset range [1, 2^n) into Gray-index ranges:
+    the range sums (each seeded from its first subset) add up to perm(A) mod p
+    from the definition, up to the sign (-1)^n."""
+    p = 1073742209
+    A = E.random_residues(n, p, E.rng(907, n))
+    want = O.reference.bruteforce_mod(A.tolist(), p)
+    g = random.Random(n)
+    end = 1 << n
+    for _ in range(6):
+        cuts = sorted({1, end, *(g.randrange(1, end + 1) for _ in range(g.randrange(0, 5)))})
+        tot = sum(O.native.ryser_modp_range(A, p, a, b) for a, b in zip(cuts, cuts[1:])) % p
+        assert ((p - tot) % p if n % 2 else tot) == want
+    assert O.native.ryser_modp_threaded(A, p, threads=3) == want
+
+
+def test_ryser_modp_threaded_equals_laplace(O):
+    g = random.Random(6)
+    for n in (10, 13):
+        A = [[g.randrange(-40, 41) for _ in range(n)] for _ in range(n)]
+        exact = O.reference.laplace(A)
+        p = 2147483647
+        R = np.array([[a % p for a in row] for row in A], dtype=np.uint32)
+        assert O.native.ryser_modp_threaded(R, p, threads=5) == exact % p
+
+
+def test_glynn_range_threaded_is_the_plain_range(O):
+    n, p = 12, 1073742209
+    M = E.random_residues(n, p, E.rng(908, 0))
+    A = _cplx(n, 908)
+    for x0, x1 in [(0, 1 << 11), (5, 1999), (100, 101)]:
+        assert O.native.glynn_range_threaded(M, x0, x1, "modp", p, threads=4) == \
+            O.native.glynn_range_modp(M, p, x0, x1)
+        whole = O.native.glynn_range_c128(A, x0, x1)
+        got = O.native.glynn_range_threaded(A, x0, x1, "c128", threads=4)
+        assert abs(got - whole) <= 1e-13 * float(np.prod(np.linalg.norm(A, axis=1))) * (x1 - x0)
 
 
 def test_crt_factorial_and_sign(O):
