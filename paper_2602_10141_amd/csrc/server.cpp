@@ -330,7 +330,30 @@ int launch_items(perm_srv *S, const std::vector<WaveItem> &items,
     return PERM_OK;
 }
 
-// Complete a finished slice: publish results of its finishing requests.
+// Mark a request finished with `status` (with mu held); a request already
+// finished (failed, cancelled) is never revived.
+void finish_locked(perm_srv *S, Req &r, int status, double t)
+{
+    if (r.state == R_DONE) return;
+    r.state = R_DONE;
+    r.status = r.cancel ? PERM_ECANCELED : status;
+    r.t_done = t;
+    r.next = r.nitems;                   // nothing more of it is scheduled
+    if (r.status == PERM_OK) {
+        S->st.completed++;
+        S->lat_us.push_back(t - r.t_submit);
+    } else if (r.status == PERM_ECANCELED) {
+        S->st.canceled++;
+    } else {
+        S->st.failed++;
+    }
+}
+
+// Complete a slice whose device work has ended: publish the results of its
+// finishing requests.  With status != PERM_OK (the slice's device work
+// failed, or it failed to launch) every request with items in it fails: its
+// partial sums are incomplete.  A request's device memory and slot are
+// released once no slice in flight carries its items.
 void complete_slice(perm_srv *S, Slice &sl, int status)
 {
     std::lock_guard<std::mutex> lk(S->mu);
@@ -338,21 +361,16 @@ void complete_slice(perm_srv *S, Slice &sl, int status)
     const size_t res_off = sl.pinned_cap - 16 * (size_t)S->cfg.max_inflight;
     for (size_t q = 0; q < sl.finishing.size(); ++q) {
         auto it = S->reqs.find(sl.finishing[q]);
-        if (it == S->reqs.end()) continue;
+        if (it == S->reqs.end() || it->second.state == R_DONE) continue;
         Req &r = it->second;
-        std::memcpy(r.result, (char *)sl.pinned + res_off + 16 * q, 16);
-        r.state = R_DONE;
-        r.status = r.cancel ? PERM_ECANCELED : status;
-        r.t_done = t;
-        if (r.status == PERM_OK) {
-            S->st.completed++;
-            S->lat_us.push_back(t - r.t_submit);
-        } else if (r.status == PERM_ECANCELED) {
-            S->st.canceled++;
-        } else {
-            S->st.failed++;
-        }
+        if (status == PERM_OK) std::memcpy(r.result, (char *)sl.pinned + res_off + 16 * q, 16);
+        finish_locked(S, r, status, t);
     }
+    if (status != PERM_OK)
+        for (uint64_t tk : sl.touched) {
+            auto it = S->reqs.find(tk);
+            if (it != S->reqs.end()) finish_locked(S, it->second, status, t);
+        }
     for (uint64_t tk : sl.touched) {
         auto it = S->reqs.find(tk);
         if (it != S->reqs.end()) it->second.inflight_slices--;
@@ -441,7 +459,7 @@ int run_slice(perm_srv *S, bool *launched)
         double oldest_t = 1e300;
         for (uint64_t t : S->admitted) {
             Req &r = S->reqs[t];
-            if (r.cancel || r.next >= r.nitems) continue;
+            if (r.cancel || r.state == R_DONE || r.next >= r.nitems) continue;
             order.push_back(t);
             if (r.t_submit < oldest_t) { oldest_t = r.t_submit; oldest = t; }
         }
@@ -482,6 +500,11 @@ int run_slice(perm_srv *S, bool *launched)
         }
     }
     if (fresh.empty() && items.empty() && fin.empty()) return PERM_OK;
+    // From here on the slice owns these requests' items: if anything below
+    // fails, the worker fails exactly the requests listed here.
+    sl.finishing = fin_t;
+    sl.touched = touched;
+    sl.work = 0;
     if (items.size() > kSliceItems) return permi::fail(PERM_EINVAL, "slice item overflow");
     // every item must stay inside its request's Gray range and partial slots
     for (size_t q = 0; q < items.size(); ++q) {
@@ -582,9 +605,6 @@ int run_slice(perm_srv *S, bool *launched)
                                hipMemcpyDeviceToHost, s));
     }
     SRV_HIP(hipEventRecord(sl.done, s));
-    sl.finishing = fin_t;
-    sl.touched = touched;
-    sl.work = 0;
     for (size_t q = 0; q < items.size(); ++q) sl.work += item_work(items[q], in_[q]);
     sl.nitems = items.size();
     sl.launch_us = now_us();
@@ -606,7 +626,7 @@ bool has_work_locked(perm_srv *S)
     if (!S->pending.empty() && !S->free_slots.empty()) return true;
     for (uint64_t t : S->admitted) {
         const Req &r = S->reqs.at(t);
-        if (!r.cancel && r.next < r.nitems) return true;
+        if (!r.cancel && r.state != R_DONE && r.next < r.nitems) return true;
     }
     return false;
 }
@@ -631,21 +651,20 @@ void worker_main(perm_srv *S)
         }
         if (work) {
             if (run_slice(S, &launched) != PERM_OK) {
-                // fail everything admitted; keep serving new requests
-                std::lock_guard<std::mutex> lk(S->mu);
-                for (uint64_t t : S->admitted) {
-                    Req &r = S->reqs[t];
-                    if (r.state != R_DONE) {
-                        r.state = R_DONE;
-                        r.status = PERM_EDEVICE;
-                        r.t_done = now_us();
-                        S->st.failed++;
-                    }
-                    S->arena.release(r.off, r.bytes);
-                    S->free_slots.push_back(r.slot);
-                }
-                S->admitted.clear();
-                S->cv_done.notify_all();
+                // The slice on stream `cur` failed to launch (part of it may
+                // have been issued) or an earlier slice's device work failed.
+                // First drain both streams, so that no issued work still
+                // reads or writes a request's arena range or descriptor slot
+                // when it is released; then the other stream's slice
+                // completes as its event says, and every request with items
+                // in the failed slice fails.  Requests it did not touch keep
+                // being served.
+                for (hipStream_t st : S->streams) (void)hipStreamSynchronize(st);
+                Slice &other = S->slices[S->cur ^ 1];
+                if (other.busy)
+                    complete_slice(S, other, hipEventQuery(other.done) == hipSuccess ? PERM_OK
+                                                                                     : PERM_EDEVICE);
+                complete_slice(S, S->slices[S->cur], PERM_EDEVICE);
                 launched = true;
             }
         }

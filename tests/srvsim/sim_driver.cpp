@@ -38,6 +38,9 @@ int main()
     const double rate = env_f("SIM_RATE", 0);                 // requests per second, 0 = at once
     const int reps = (int)env_f("SIM_REPS", 1);
     const int cancel_every = (int)env_f("SIM_CANCEL_EVERY", 0);
+    // with fault injection on, requests may fail with PERM_EDEVICE; all
+    // others must still complete with their own results
+    const bool faults = getenv("SIM_FAIL_WALK") || getenv("SIM_FAIL_EVENT_SYNC");
     std::vector<int> big;
     {
         std::stringstream ss(getenv("SIM_BIG") ? getenv("SIM_BIG") : "32,34,36");
@@ -70,6 +73,7 @@ int main()
     ctx.num_cus = 256;
     long wrong = 0;
     for (int rep = 0; rep < reps && !wrong; ++rep) {
+        long failed = 0;
         perm_srv_cfg cfg{};
         cfg.hbm_budget = (size_t)env_f("SIM_BUDGET_MB", 512) << 20;
         cfg.max_inflight = (int)env_f("SIM_MAX_INFLIGHT", 0);
@@ -110,6 +114,10 @@ int main()
                 _Exit(3);
             }
             if (cancel_every && i % cancel_every == 0 && rc == PERM_ECANCELED) continue;
+            if (faults && rc == PERM_EDEVICE) {
+                ++failed;
+                continue;
+            }
             uint64_t h, bad;
             memcpy(&h, out, 8);
             memcpy(&bad, out + 8, 8);
@@ -128,10 +136,22 @@ int main()
         perm_srv_stats st{};
         perm_srv_get_stats(S, &st);
         perm_srv_destroy(S);
-        printf("rep %d: wrong %ld desync %ld bad_slots %ld items %ld slices %llu completed %llu canceled %llu\n",
+        // every request is counted once: completed, failed or cancelled
+        if (st.completed + st.failed + st.canceled != st.submitted) {
+            fprintf(stderr, "stats: %llu completed + %llu failed + %llu canceled != %llu submitted\n",
+                    (unsigned long long)st.completed, (unsigned long long)st.failed,
+                    (unsigned long long)st.canceled, (unsigned long long)st.submitted);
+            wrong++;
+        }
+        if (st.failed != (uint64_t)failed) {
+            fprintf(stderr, "stats count %llu failed, the results %ld\n",
+                    (unsigned long long)st.failed, failed);
+            wrong++;
+        }
+        printf("rep %d: wrong %ld desync %ld bad_slots %ld items %ld slices %llu completed %llu canceled %llu failed %ld\n",
                rep, wrong, sim_desync.load(), sim_bad_parts.load(), sim_items.load(),
                (unsigned long long)st.slices, (unsigned long long)st.completed,
-               (unsigned long long)st.canceled);
+               (unsigned long long)st.canceled, failed);
     }
     fflush(stdout);
     fflush(stderr);

@@ -61,6 +61,11 @@ int launch_walk(int, int, bool, bool, int, const WaveItem *d_items, uint32_t cou
                 unsigned long long *ctr, CtrState *state, int grid_blocks, void *stream,
                 const void *fin_src, void *fin_out, int fin_nmats)
 {
+    // Fault injection: SIM_FAIL_WALK=k makes the k-th walk launch fail
+    // (nothing of it is enqueued), as a failed kernel launch would.
+    static std::atomic<long> launches{0};
+    static const long fail_at = getenv("SIM_FAIL_WALK") ? atol(getenv("SIM_FAIL_WALK")) : 0;
+    if (fail_at > 0 && ++launches == fail_at) return 1;
     if (fin_nmats) return 1;      // the request loop always stages and finalizes separately
     (void)fin_src;
     (void)fin_out;
@@ -80,6 +85,10 @@ int launch_walk(int, int, bool, bool, int, const WaveItem *d_items, uint32_t cou
             for (uint64_t idx = r * per_run; idx < end; ++idx) {
                 const WaveItem &w = d_items[idx];
                 const MatDesc &d = d_mats[w.mat];
+                // the descriptor slot still belongs to this item's request:
+                // a slot handed to a new request while the item was in
+                // flight shows up as a partial range that does not hold it
+                if (w.slot < d.first_part || w.slot >= d.first_part + d.num_parts) sim_bad_parts++;
                 uint64_t *slot = (uint64_t *)((char *)partials + 16 * (size_t)w.slot);
                 slot[0] = *(const uint64_t *)((const char *)stage + d.stage_off);
                 slot[1] = w.x0;

@@ -1,6 +1,7 @@
 // Command-queue implementation of the HIP runtime test double.
 #include "hip/hip_runtime.h"
 
+#include <atomic>
 #include <chrono>
 #include <condition_variable>
 #include <cstdio>
@@ -202,8 +203,14 @@ hipError_t hipEventRecord(hipEvent_t e, hipStream_t s)
     push_locked(s, std::move(c));
     return hipSuccess;
 }
+// Fault injection: SIM_FAIL_EVENT_SYNC=k makes the k-th hipEventSynchronize
+// report an error once the event has completed (a device error noticed when
+// the host waits for a slice).
 hipError_t hipEventSynchronize(hipEvent_t e)
 {
+    static std::atomic<long> calls{0};
+    static const long fail_at = getenv("SIM_FAIL_EVENT_SYNC") ? atol(getenv("SIM_FAIL_EVENT_SYNC")) : 0;
+    const bool fail = fail_at > 0 && ++calls == fail_at;
     uint64_t g;
     {
         std::lock_guard<std::mutex> lk(mu);
@@ -213,7 +220,7 @@ hipError_t hipEventSynchronize(hipEvent_t e)
     for (;;) {
         {
             std::lock_guard<std::mutex> lk(mu);
-            if (e->completed >= g) return hipSuccess;
+            if (e->completed >= g) return fail ? hipErrorInvalidValue : hipSuccess;
         }
         if (now_ms() - t0 > 30000) {
             fprintf(stderr, "SIM: an event wait took 30 s: the command queues are stuck\n");

@@ -54,6 +54,26 @@ def test_served_results_intact(sim, scenario):
     assert "wrong 0 desync 0 bad_slots 0" in out, out
 
 
+@pytest.mark.parametrize("scenario", [
+    dict(rate=0, seed=11, ns_per_item=100, fail_walk=5),            # a walk launch fails
+    dict(rate=0, seed=12, ns_per_item=100, fail_event_sync=4),      # a slice's event reports an error
+    dict(rate=3000, seed=13, ns_per_item=100, fail_walk=9),         # paced, mid-stream
+    dict(rate=0, seed=14, budget_mb=40, ns_per_item=50, fail_walk=3),   # memory-bound admission
+    dict(rate=0, seed=15, cancel_every=3, budget_mb=40, fail_event_sync=7),
+], ids=["walk_burst", "event_burst", "walk_paced", "walk_budget", "event_cancel"])
+def test_device_errors_fail_only_the_affected_requests(sim, scenario):
+    """Fault injection in the runtime double: a failed walk launch or an
+    event that reports an error.  The requests with work in the failed slice
+    report PERM_EDEVICE; every other request completes with its own result;
+    no descriptor slot or arena range is handed to a new request while work
+    of the old one is in flight (checked by every walk item and finalize);
+    the statistics count each request once."""
+    out = run(sim, **scenario)
+    assert "wrong 0 desync 0 bad_slots 0" in out, out
+    failed = int(out.split("failed ")[-1].split()[0])
+    assert failed >= 1, out
+
+
 def test_repeated_servers_in_one_process(sim):
     out = run(sim, rate=0, seed=7, reps=3, big="26,28,30")
     assert out.count("wrong 0 desync 0 bad_slots 0") == 3, out
@@ -61,11 +81,13 @@ def test_repeated_servers_in_one_process(sim):
 
 @pytest.mark.slow
 def test_no_data_races(tmp_path):
-    """ThreadSanitizer over a burst and a paced stream (clang's runtime)."""
+    """ThreadSanitizer over a burst, a paced stream and a failed walk launch
+    (clang's runtime)."""
     if not os.path.exists(CLANG):
         pytest.skip("clang with ThreadSanitizer not available")
     b = _build(str(tmp_path / "srvsim_tsan"), CLANG, ["-O1", "-fsanitize=thread"])
-    for sc in (dict(rate=0, seed=8), dict(rate=2000, seed=9, cancel_every=4, budget_mb=40)):
+    for sc in (dict(rate=0, seed=8), dict(rate=2000, seed=9, cancel_every=4, budget_mb=40),
+               dict(rate=0, seed=10, ns_per_item=50, fail_walk=4)):
         env = dict(sc, big="26,28,30")
         e = dict(os.environ, TSAN_OPTIONS="halt_on_error=1 exitcode=66")
         e.update({f"SIM_{k.upper()}": str(v) for k, v in env.items()})
