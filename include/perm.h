@@ -89,6 +89,25 @@ const char *perm_last_error(void);
  * Errors: PERM_EINVAL (n out of range, NULL pointer), PERM_ENOMEM, PERM_EDEVICE. */
 int perm_c128(perm_ctx *ctx, const double *A, int n, double *out, unsigned flags, void *stream);
 
+/* perm_c128 for callers that cannot allocate device memory: code under HIP
+ * graph capture, tight serving loops, harnesses that forbid hipMalloc.  The
+ * call makes no hipMalloc, hipFree or host-to-device copy: its scratch
+ * (work counters, the work partition, partial sums, staged columns) is a
+ * static device array of 2 MiB per device, which the library holds until the
+ * process ends, and a kernel writes the partition into it.  Same partition
+ * and kernels as perm_c128, so the same bits.
+ * A: device, n*n complex128 row-major, 8-byte aligned.  out: device, 2
+ * doubles (re, im), 8-byte aligned.  flags must contain PERM_DEVICE_PTRS
+ * (PERM_NO_KAHAN allowed); asynchronous on `stream` (NULL: the context's).
+ * 0 <= n <= 32.  Every call on a device shares that device's scratch: calls
+ * that overlap on one device (different streams, contexts or threads) race;
+ * calls on one stream are ordered.
+ * Errors: PERM_EINVAL (host pointers, other flags, n out of range,
+ * misalignment, NULL), PERM_ENOMEM (the tuning table's chunk length for n
+ * needs more wave items than the scratch holds), PERM_EDEVICE. */
+int perm_c128_noalloc(perm_ctx *ctx, const double *A, int n, double *out, unsigned flags,
+                      void *stream);
+
 /* perm of one float64 matrix.  A: dev-or-host n*n.  out: dev-or-host, 1 double. */
 int perm_f64(perm_ctx *ctx, const double *A, int n, double *out, unsigned flags, void *stream);
 

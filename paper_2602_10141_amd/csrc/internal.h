@@ -92,6 +92,8 @@ struct perm_ctx {
     std::vector<permi::MatIn> plan_in;
     std::vector<std::pair<std::pair<int, int>, int>> plan_chunks;
     bool plan_cached = false;
+    // device address of the static scratch of perm_c128_noalloc on this device
+    void *noalloc_ptr = nullptr;
     uint64_t plan_id = 0, uploaded_plan_id = ~0ull;
     const void *uploaded_ptr = nullptr;
 };

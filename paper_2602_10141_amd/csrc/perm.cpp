@@ -24,6 +24,7 @@
 #include "../../include/perm.h"
 #include "internal.h"
 #include "kernels.h"
+#include "noalloc.h"
 #include "numth.h"
 
 using namespace permk;
@@ -546,6 +547,14 @@ extern "C" int perm_ctx_create(int device, size_t hbm_budget, perm_ctx **out)
         return fail(PERM_EDEVICE, "counter init failed");
     }
     c->ctr_state = CtrState{};
+    // the static scratch of perm_c128_noalloc: its device address on this
+    // device (the device is current here)
+    const int se = noalloc_scratch_init(device, &c->noalloc_ptr);
+    if (se != (int)hipSuccess) {
+        perm_ctx_destroy(c);
+        return fail(PERM_EDEVICE, "static scratch lookup failed on device %d: %s", device,
+                    hipGetErrorString((hipError_t)se));
+    }
     *out = c;
     return PERM_OK;
 }
@@ -659,6 +668,89 @@ extern "C" int perm_modp(perm_ctx *ctx, const uint32_t *A, int n, uint32_t p, ui
 {
     if (!modulus_ok(p)) return fail(PERM_EINVAL, "modulus %u must be odd with 3 <= p < 2^31", p);
     return single(ctx, variant_of(PERM_MODP, flags), A, n, p, out, 4, flags, stream);
+}
+
+// ------------------------------------------------------ no-allocation c128
+// perm_c128 for callers that cannot allocate: device pointers only, every
+// byte of device scratch in the static array of noalloc.hip, the partition
+// written there by a kernel.  The partition and launch shape are those
+// plan() and execute() give one whole c128 matrix, so the result has
+// perm_c128's bits.  No host heap allocation either.
+extern "C" int perm_c128_noalloc(perm_ctx *ctx, const double *A, int n, double *out,
+                                 unsigned flags, void *stream)
+{
+    if (!ctx) return fail(PERM_EINVAL, "ctx is NULL");
+    if (!(flags & PERM_DEVICE_PTRS))
+        return fail(PERM_EINVAL, "perm_c128_noalloc takes device pointers only (PERM_DEVICE_PTRS)");
+    if (flags & ~(PERM_DEVICE_PTRS | PERM_NO_KAHAN))
+        return fail(PERM_EINVAL, "perm_c128_noalloc: unsupported flags 0x%x", flags);
+    if (n < 0 || n > NOALLOC_NMAX)
+        return fail(PERM_EINVAL, "n = %d outside [0, %d], the orders of the no-allocation call", n,
+                    NOALLOC_NMAX);
+    if (!out || (n > 0 && !A)) return fail(PERM_EINVAL, "NULL matrix or output pointer");
+    if ((uintptr_t)out % 8 || (uintptr_t)A % 8)
+        return fail(PERM_EINVAL, "matrix and output must be 8-byte aligned");
+    if (!ctx->noalloc_ptr) return fail(PERM_EDEVICE, "no static scratch on device %d", ctx->device);
+    const bool kahan = !(flags & PERM_NO_KAHAN);
+    // split_range over the whole of [0, 2^(n-1)): equal items of 64 lanes x
+    // 2^c indices, or one item of fewer indices for a short range
+    uint64_t count = 0;
+    uint32_t log2L = 0, nlanes = 0;
+    if (n > 0) {
+        const int c = log2_chunk_for(ctx, V_C128, n);
+        const uint64_t T = 1ull << (n - 1);
+        const uint64_t W = 64ull << c;
+        if (T >= W) {
+            count = T / W;
+            log2L = (uint32_t)c;
+            nlanes = 64;
+        } else if (T >= 64) {
+            count = 1;
+            log2L = (uint32_t)(n - 7);
+            nlanes = 64;
+        } else {
+            count = 1;
+            nlanes = (uint32_t)T;
+        }
+    }
+    NoallocLayout L{};
+    if (count > (1u << 20) || noalloc_layout(n, (uint32_t)count, &L) != 0)
+        return fail(PERM_ENOMEM,
+                    "order %d in %llu wave items needs more than the %zu bytes of static scratch",
+                    n, (unsigned long long)count, NOALLOC_SCRATCH_BYTES);
+    hipStream_t s = stream ? (hipStream_t)stream : ctx->stream;
+    int rc = begin_call(ctx, s);
+    if (rc != PERM_OK) return rc;
+    char *base = (char *)ctx->noalloc_ptr;
+    HIPCHK((hipError_t)launch_noalloc_plan(base, &L, (uint32_t)count, n, log2L, nlanes,
+                                           kahan ? MD_KAHAN : 0u, out, s));
+    if (n > 0) {
+        // launch shape as execute() picks it for this one group
+        int occ = 0;
+        const int key = V_C128 * 200 + n * 2 + (kahan ? 1 : 0);
+        auto it = ctx->occ.find(key);
+        if (it != ctx->occ.end()) occ = it->second;
+        else if (walk_occupancy(V_C128, n, kahan, false, 0, &occ) != 0 || occ < 1) occ = 1;
+        const int per_cu = ctx->grid_per_cu > 0 ? std::min(ctx->grid_per_cu, occ) : occ;
+        const uint32_t cnt = (uint32_t)count;
+        const uint32_t resident = (uint32_t)(per_cu * ctx->num_cus * (BLOCK / WAVE));
+        const uint32_t grab = std::max(1u, std::min(grab_for(log2L), cnt / (2 * resident)));
+        const uint32_t runs = (cnt + grab * (BLOCK / WAVE) - 1) / (grab * (BLOCK / WAVE));
+        const int grid = (int)std::max(1u, std::min(runs, (uint32_t)(per_cu * ctx->num_cus)));
+        const bool one_block = grid == 1;
+        const MatDesc *d_mats = (const MatDesc *)(base + L.mat);
+        void *stage = base + L.stage;
+        double *partials = (double *)(base + L.partials);
+        if (!one_block) HIPCHK((hipError_t)launch_stage(d_mats, 1, A, stage, s));
+        CtrState st{};                      // the plan kernel zeroed the counters
+        HIPCHK((hipError_t)launch_walk(V_C128, n, kahan, false, 0,
+                                       (const WaveItem *)(base + L.items), cnt, grab, d_mats, stage,
+                                       partials, (unsigned long long *)(base + L.ctr), &st, grid, s,
+                                       one_block ? A : nullptr, one_block ? out : nullptr,
+                                       one_block ? 1 : 0));
+        if (!one_block) HIPCHK((hipError_t)launch_finalize(d_mats, 1, partials, out, s));
+    }
+    return end_call(ctx, s);
 }
 
 // ------------------------------------------------------------------- batch

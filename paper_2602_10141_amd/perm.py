@@ -64,6 +64,7 @@ _SIGS = {
     "perm_strerror": ([_I], ctypes.c_char_p),
     "perm_last_error": ([], ctypes.c_char_p),
     "perm_c128": ([_P, _P, _I, _P, _U, _P], _I),
+    "perm_c128_noalloc": ([_P, _P, _I, _P, _U, _P], _I),
     "perm_f64": ([_P, _P, _I, _P, _U, _P], _I),
     "perm_modp": ([_P, _P, _I, ctypes.c_uint32, _P, _U, _P], _I),
     "perm_crt_int": ([_P, _P, _P, _I, _I, _D, _P, _I, _P, _P, _P, _U, _P], _I),
@@ -192,6 +193,23 @@ def perm_c128(ctx, A, flags=0, stream=None):
     _check(lib().perm_c128(ctx.ptr, A.ctypes.data, A.shape[0] if A.ndim == 2 else 0,
                            out.ctypes.data, flags & ~PERM_DEVICE_PTRS, None))
     return complex(out[0], out[1])
+
+
+def perm_c128_noalloc(ctx, A, out=None, flags=0, stream=None):
+    """perm(A) with no allocation inside the library (static device scratch).
+    A: contiguous complex128 CUDA tensor, n <= 32.  out: a CUDA float64 tensor
+    of 2 elements to write (re, im) into, or None for a new one; asynchronous
+    on torch's current stream (or `stream`)."""
+    if not _is_dev(A) or A.dtype != torch.complex128:
+        raise TypeError("perm_c128_noalloc needs a complex128 CUDA tensor")
+    if A.dim() != 2 or A.shape[0] != A.shape[1] or not A.is_contiguous():
+        raise ValueError("expected a contiguous square CUDA tensor")
+    if out is None:
+        out = torch.empty(2, dtype=torch.float64, device=A.device)
+    _check(lib().perm_c128_noalloc(ctx.ptr, ctypes.c_void_p(A.data_ptr()), A.shape[0],
+                                   ctypes.c_void_p(out.data_ptr()), flags | PERM_DEVICE_PTRS,
+                                   _stream(stream)))
+    return out
 
 
 def perm_f64(ctx, A, flags=0, stream=None):
