@@ -166,7 +166,10 @@ int perm_range(perm_ctx *ctx, const perm_item *item, const void *data, uint64_t 
 /* Walk-kernel timing.  While enabled, the context records a pair of HIP
  * events around every walk-kernel launch, on the stream the kernel runs on
  * (a launch of one block that stages and finalizes its call's matrices
- * includes that work).  Enabling creates events for 256 launches up front;
+ * includes that work; a server created on the context records its walk
+ * launches too).  Enabling creates events for max(256, on) launches up front
+ * (at most 65,536); past that, library calls create more while a server's
+ * launches go unrecorded;
  * recording a pair still adds about 9 us to a call's turnaround on the
  * stream, so time small calls' throughput with timing off.  perm_prof_read waits for the
  * recorded launches, returns their summed device time in milliseconds and
@@ -195,6 +198,19 @@ int perm_schur_residues(int n, uint32_t p, uint32_t *out);
  * elsewhere, e.g. by perm_range over split ranges). */
 int perm_crt_lift(const uint32_t *residues, const uint32_t *primes, int k, double log2_bound,
                   uint64_t *limbs, int max_limbs, int *nlimbs, int *sign);
+
+/* Redundant-prime check of a CRT result, for long exact runs (paper Sec. 2.1
+ * lifts one residue per prime; with one prime more than the bound needs, a
+ * residue corrupted by a device or memory fault is detected and named).
+ * Lifts all k residues and each of the k subsets that leave one out; every
+ * such subset's product must still exceed 2^(log2_bound + 1) (else
+ * PERM_ERANGE).  All k + 1 lifts equal: *bad = -1 and the value.  Otherwise,
+ * if exactly one left-out residue j gives a lift with |X| <= 2^log2_bound,
+ * residue j is the corrupted one: *bad = j and that lift is the value.
+ * Otherwise PERM_ERANGE ("residues inconsistent").  Outputs as in
+ * perm_crt_lift.  Host-only. */
+int perm_crt_check(const uint32_t *residues, const uint32_t *primes, int k, double log2_bound,
+                   uint64_t *limbs, int max_limbs, int *nlimbs, int *sign, int *bad);
 
 /* -------------------------------------------------------- checkpointed job
  * An exact integer permanent from k residue matrices (as perm_crt_int) for
@@ -252,7 +268,12 @@ int perm_tune_set(perm_ctx *ctx, int field, int n, const perm_tune *t);
 int perm_autotune(perm_ctx *ctx, int field, int n_lo, int n_hi, int batch);
 
 /* Save / load the table as text lines "field n log2_chunk grid_per_cu",
- * keyed in the file header by the device's gcnArchName. */
+ * keyed by the header lines "# arch <gcnArchName>" and "# hip <HIP runtime
+ * version>".  Loading checks the key against the context's device and the
+ * running HIP runtime, and every line (F_p chunk lengths at most 20): a
+ * table without the key lines, tuned for another architecture or runtime,
+ * or with a bad line is refused with PERM_EINVAL and the context's table is
+ * left as it was. */
 int perm_tune_save(perm_ctx *ctx, const char *path);
 int perm_tune_load(perm_ctx *ctx, const char *path);
 

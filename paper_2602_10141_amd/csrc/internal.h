@@ -3,6 +3,7 @@
 #include <hip/hip_runtime.h>
 
 #include <map>
+#include <mutex>
 #include <string>
 #include <utility>
 #include <vector>
@@ -80,6 +81,9 @@ struct perm_ctx {
     std::map<std::pair<int, int>, perm_tune> tune;
     std::map<int, int> occ;
     bool prof_on = false;
+    // walk-launch timing events; a server's worker thread records into them
+    // too, so they are guarded
+    std::mutex prof_mu;
     std::vector<std::pair<hipEvent_t, hipEvent_t>> prof_pending, prof_pool;
     // host scratch reused across calls (keeps its capacity: large batches
     // would otherwise fault in fresh pages on every call)

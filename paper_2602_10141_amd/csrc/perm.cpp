@@ -480,16 +480,24 @@ int execute(perm_ctx *ctx, Plan &pl, const void *src, void *out, size_t out_slot
         const Group &g = pl.groups[q];
         if (!g.count) continue;
         std::pair<hipEvent_t, hipEvent_t> ev{nullptr, nullptr};
-        if (ctx->prof_on) {
-            if (ctx->prof_pool.empty()) {
-                HIPCHK(hipEventCreate(&ev.first));
-                HIPCHK(hipEventCreate(&ev.second));
-            } else {
+        bool prof = false;
+        {
+            std::lock_guard<std::mutex> lk(ctx->prof_mu);
+            if (ctx->prof_on && !ctx->prof_pool.empty()) {
                 ev = ctx->prof_pool.back();
                 ctx->prof_pool.pop_back();
+                prof = true;
             }
-            HIPCHK(hipEventRecord(ev.first, s));
         }
+        if (ctx->prof_on && !prof) {          // pool used up: one more pair
+            HIPCHK(hipEventCreate(&ev.first));
+            if (hipEventCreate(&ev.second) != hipSuccess) {
+                (void)hipEventDestroy(ev.first);
+                return fail(PERM_EDEVICE, "hipEventCreate failed");
+            }
+            prof = true;
+        }
+        if (prof) HIPCHK(hipEventRecord(ev.first, s));
         HIPCHK((hipError_t)launch_walk(g.variant, g.n, g.kahan, g.fused, g.nmax_fused,
                                        d_items + g.first_item, g.count, shape[q].grab, d_mats,
                                        ctx->stage.p, (double *)ctx->partials.p,
@@ -497,8 +505,9 @@ int execute(perm_ctx *ctx, Plan &pl, const void *src, void *out, size_t out_slot
                                        shape[q].grid, s, one_block ? src : nullptr,
                                        one_block ? out : nullptr,
                                        one_block ? (int)pl.mats.size() : 0));
-        if (ctx->prof_on) {
+        if (prof) {
             HIPCHK(hipEventRecord(ev.second, s));
+            std::lock_guard<std::mutex> lk(ctx->prof_mu);
             ctx->prof_pending.push_back(ev);
         }
     }
@@ -909,6 +918,60 @@ extern "C" int perm_crt_lift(const uint32_t *residues, const uint32_t *primes, i
     return write_limbs(mag, sg, limbs, max_limbs, nlimbs, sign);
 }
 
+// log2 of a nonzero multi-limb magnitude (to about 1e-15 relative).
+static double log2_big(const permh::BigU &m)
+{
+    const size_t L = m.limb.size();
+    double top = (double)m.limb[L - 1];
+    if (L >= 2) top += std::ldexp((double)m.limb[L - 2], -64);
+    return std::log2(top) + 64.0 * (double)(L - 1);
+}
+
+extern "C" int perm_crt_check(const uint32_t *residues, const uint32_t *primes, int k,
+                              double log2_bound, uint64_t *limbs, int max_limbs, int *nlimbs,
+                              int *sign, int *bad)
+{
+    if (!residues || !limbs || !nlimbs || !sign || !bad) return fail(PERM_EINVAL, "NULL argument");
+    int rc = check_primes(primes, k, log2_bound);
+    if (rc != PERM_OK) return rc;
+    if (k < 2) return fail(PERM_ERANGE, "a redundancy check needs at least two primes");
+    std::vector<uint32_t> r(residues, residues + k), p(primes, primes + k);
+    // every leave-one-out subset must still determine the integer
+    for (int j = 0; j < k; ++j) {
+        const double l = permh::log2_product(primes, k) - std::log2((double)primes[j]);
+        if (l <= log2_bound + 1.0 + 1e-9)
+            return fail(PERM_ERANGE, "without prime %u the product 2^%.3f does not exceed "
+                        "2^(%.3f + 1): no redundant prime", primes[j], l, log2_bound);
+    }
+    permh::BigU all_m, m;
+    int all_s = 0, sg = 0;
+    if (!permh::garner_lift(r.data(), p.data(), k, all_m, all_s)) return fail(PERM_EINVAL, "lift failed");
+    std::vector<permh::BigU> lm(k);
+    std::vector<int> ls(k);
+    bool agree = true;
+    for (int j = 0; j < k; ++j) {
+        std::vector<uint32_t> rj, pj;
+        for (int i = 0; i < k; ++i)
+            if (i != j) { rj.push_back(r[i]); pj.push_back(p[i]); }
+        if (!permh::garner_lift(rj.data(), pj.data(), k - 1, lm[j], ls[j]))
+            return fail(PERM_EINVAL, "lift failed");
+        agree = agree && ls[j] == all_s && permh::BigU::cmp(lm[j], all_m) == 0;
+    }
+    if (agree) {
+        *bad = -1;
+        return write_limbs(all_m, all_s, limbs, max_limbs, nlimbs, sign);
+    }
+    // one corrupted residue: only the lift that leaves it out is within the bound
+    int cand = -1, ncand = 0;
+    for (int j = 0; j < k; ++j)
+        if (ls[j] == 0 || log2_big(lm[j]) <= log2_bound) { cand = j; ++ncand; }
+    if (ncand != 1)
+        return fail(PERM_ERANGE, "residues inconsistent: %d leave-one-out lifts fall within the "
+                    "bound, so no single residue can be named", ncand);
+    *bad = cand;
+    return write_limbs(lm[cand], ls[cand], limbs, max_limbs, nlimbs, sign);
+}
+
 extern "C" int perm_crt_int(perm_ctx *ctx, const uint32_t *mats, const uint32_t *primes, int k,
                             int n, double log2_bound, uint64_t *limbs, int max_limbs, int *nlimbs,
                             int *sign, uint32_t *residues_out, unsigned flags, void *stream)
@@ -956,11 +1019,13 @@ extern "C" int perm_crt_int(perm_ctx *ctx, const uint32_t *mats, const uint32_t 
 extern "C" int perm_prof_enable(perm_ctx *ctx, int on)
 {
     if (!ctx) return fail(PERM_EINVAL, "ctx is NULL");
+    std::lock_guard<std::mutex> lk(ctx->prof_mu);
     if (on) {
-        // event pairs for the next 256 launches, created here rather than
-        // inside timed calls
+        // event pairs for the next max(256, on) launches, created here
+        // rather than inside timed calls
         HIPCHK(hipSetDevice(ctx->device));
-        while (ctx->prof_pool.size() + ctx->prof_pending.size() < 256) {
+        const size_t want = std::max(256, std::min(on, 1 << 16));
+        while (ctx->prof_pool.size() + ctx->prof_pending.size() < want) {
             std::pair<hipEvent_t, hipEvent_t> ev{nullptr, nullptr};
             HIPCHK(hipEventCreate(&ev.first));
             if (hipEventCreate(&ev.second) != hipSuccess) {
@@ -977,6 +1042,7 @@ extern "C" int perm_prof_enable(perm_ctx *ctx, int on)
 extern "C" int perm_prof_read(perm_ctx *ctx, double *walk_ms, uint64_t *launches)
 {
     if (!ctx || !walk_ms || !launches) return fail(PERM_EINVAL, "NULL argument");
+    std::lock_guard<std::mutex> lk(ctx->prof_mu);
     HIPCHK(hipSetDevice(ctx->device));
     double tot = 0.0;
     for (auto &e : ctx->prof_pending) {
@@ -1052,38 +1118,82 @@ extern "C" int perm_tune_set(perm_ctx *ctx, int field, int n, const perm_tune *t
     return PERM_OK;
 }
 
+// The key of a tuning table: the device's architecture name and the HIP
+// runtime version (timings, and so the best partition, change with both).
+static int tune_key(perm_ctx *ctx, std::string &arch, int &hip_version)
+{
+    arch = ctx->arch;
+    hip_version = 0;
+    HIPCHK(hipRuntimeGetVersion(&hip_version));
+    return PERM_OK;
+}
+
 extern "C" int perm_tune_save(perm_ctx *ctx, const char *path)
 {
     if (!ctx || !path) return fail(PERM_EINVAL, "bad argument");
+    std::string arch;
+    int hv = 0;
+    int rc = tune_key(ctx, arch, hv);
+    if (rc != PERM_OK) return rc;
     FILE *f = fopen(path, "w");
     if (!f) return fail(PERM_EINVAL, "cannot open %s", path);
-    fprintf(f, "# libperm tuning table: field n log2_chunk grid_per_cu\n# arch %s\n",
-            ctx->arch.c_str());
+    fprintf(f, "# libperm tuning table: field n log2_chunk grid_per_cu\n# arch %s\n# hip %d\n",
+            arch.c_str(), hv);
     for (auto &kv : ctx->tune)
         fprintf(f, "%d %d %d %d\n", kv.first.first, kv.first.second, kv.second.log2_chunk,
                 kv.second.grid_per_cu);
-    fclose(f);
+    const bool ok = !ferror(f);
+    if (fclose(f) != 0 || !ok) return fail(PERM_EINVAL, "writing %s failed", path);
     return PERM_OK;
 }
 
 extern "C" int perm_tune_load(perm_ctx *ctx, const char *path)
 {
     if (!ctx || !path) return fail(PERM_EINVAL, "bad argument");
+    std::string arch;
+    int hv = 0;
+    int rc = tune_key(ctx, arch, hv);
+    if (rc != PERM_OK) return rc;
     FILE *f = fopen(path, "r");
     if (!f) return fail(PERM_EINVAL, "cannot open %s", path);
-    char line[256];
+    char line[512];
     std::map<std::pair<int, int>, perm_tune> tab;
+    bool have_arch = false, have_hip = false;
+    auto bad = [&](const char *why) {
+        fclose(f);
+        return fail(PERM_EINVAL, "%s: %s", path, why);
+    };
     while (fgets(line, sizeof line, f)) {
-        if (line[0] == '#' || line[0] == '\n') continue;
+        if (line[0] == '\n') continue;
+        if (line[0] == '#') {
+            char key[16] = {0}, val[400] = {0};
+            if (sscanf(line, "# %15s %399s", key, val) == 2) {
+                if (!strcmp(key, "arch")) {
+                    if (arch != val) return bad("tuned for another device architecture");
+                    have_arch = true;
+                } else if (!strcmp(key, "hip")) {
+                    if (atoi(val) != hv) return bad("tuned under another HIP runtime version");
+                    have_hip = true;
+                }
+            }
+            continue;
+        }
         int field, n, c, g;
         if (sscanf(line, "%d %d %d %d", &field, &n, &c, &g) != 4 || !tune_key_ok(field, n) || c < 0 ||
             c > 24 || g < 0) {
             fclose(f);
             return fail(PERM_EINVAL, "malformed line in %s: %s", path, line);
         }
+        if (field == PERM_MODP && c > 20) {
+            fclose(f);
+            return fail(PERM_EINVAL, "%s: F_p chunks are limited to 2^20 indices per lane: %s", path,
+                        line);
+        }
         tab[{field, n}] = perm_tune{c, g};
     }
     fclose(f);
+    if (!have_arch || !have_hip)
+        return fail(PERM_EINVAL, "%s: no '# arch' and '# hip' key lines", path);
     ctx->tune = tab;
     return PERM_OK;
 }

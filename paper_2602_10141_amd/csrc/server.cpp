@@ -320,11 +320,29 @@ int launch_items(perm_srv *S, const std::vector<WaveItem> &items,
         const uint32_t runs = (count + grab - 1) / grab;
         const int grid = std::max(1, std::min((int)((runs + 3) / 4), occ * S->ctx->num_cus));
         unsigned long long *ctr = (unsigned long long *)((char *)S->ctr_dev + CTR_BYTES * S->cur);
+        // walk-launch timing (perm_prof_enable on the context), while the
+        // context's pool of event pairs lasts
+        std::pair<hipEvent_t, hipEvent_t> ev{nullptr, nullptr};
+        bool prof = false;
+        {
+            std::lock_guard<std::mutex> lk(S->ctx->prof_mu);
+            if (S->ctx->prof_on && !S->ctx->prof_pool.empty()) {
+                ev = S->ctx->prof_pool.back();
+                S->ctx->prof_pool.pop_back();
+                prof = true;
+            }
+        }
+        if (prof) SRV_HIP(hipEventRecord(ev.first, s));
         SRV_HIP((hipError_t)launch_walk(item_variant[i], item_n[i], kahan, fz,
                                         nmax <= FUSED_BUCKETS[0] ? FUSED_BUCKETS[0] : FUSED_BUCKETS[1],
                                         d_items_base + i, count, grab, (const MatDesc *)S->table_dev,
                                         S->arena_dev, (double *)S->arena_dev, ctr,
                                         &S->ctr_state[S->cur], grid, s));
+        if (prof) {
+            SRV_HIP(hipEventRecord(ev.second, s));
+            std::lock_guard<std::mutex> lk(S->ctx->prof_mu);
+            S->ctx->prof_pending.push_back(ev);
+        }
         i = j;
     }
     return PERM_OK;

@@ -75,6 +75,7 @@ _SIGS = {
     "perm_schur_primes": ([_I, _I, _P, _I, _P], _I),
     "perm_schur_residues": ([_I, ctypes.c_uint32, _P], _I),
     "perm_crt_lift": ([_P, _P, _I, _D, _P, _I, _P, _P], _I),
+    "perm_crt_check": ([_P, _P, _I, _D, _P, _I, _P, _P, _P], _I),
     "perm_tune_get": ([_P, _I, _I, _P], _I),
     "perm_tune_set": ([_P, _I, _I, _P], _I),
     "perm_autotune": ([_P, _I, _I, _I, _I], _I),
@@ -279,6 +280,20 @@ def perm_crt_lift(residues, primes, log2_bound: float) -> int:
     return _limbs_to_int(limbs, nl.value, sg.value)
 
 
+def perm_crt_check(residues, primes, log2_bound: float):
+    """Redundant-prime check: returns (integer, index of the corrupted
+    residue or None); raises PermError (PERM_ERANGE) when the residues are
+    inconsistent beyond one corrupted residue."""
+    r = np.ascontiguousarray(residues, dtype=np.uint32)
+    p = np.ascontiguousarray(primes, dtype=np.uint32)
+    limbs = np.zeros(64, dtype=np.uint64)
+    nl, sg, bad = ctypes.c_int(), ctypes.c_int(), ctypes.c_int()
+    _check(lib().perm_crt_check(r.ctypes.data, p.ctypes.data, len(p), float(log2_bound),
+                                limbs.ctypes.data, len(limbs), ctypes.byref(nl), ctypes.byref(sg),
+                                ctypes.byref(bad)))
+    return _limbs_to_int(limbs, nl.value, sg.value), (None if bad.value < 0 else bad.value)
+
+
 def perm_schur_primes(n: int, extra: int = 0):
     buf = np.zeros(128, dtype=np.uint32)
     k = ctypes.c_int()
@@ -371,7 +386,9 @@ def perm_range(ctx, item, data, x0: int, x1: int, flags=0):
 
 # --------------------------------------------------------------- profiling
 def perm_prof_enable(ctx, on=True):
-    _check(lib().perm_prof_enable(ctx.ptr, int(bool(on))))
+    """on: False/0 disables; True or an int enables, with at least that many
+    event pairs (256 at least) created up front."""
+    _check(lib().perm_prof_enable(ctx.ptr, int(on)))
 
 
 def perm_prof_read(ctx):

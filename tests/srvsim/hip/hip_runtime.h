@@ -46,6 +46,7 @@ hipError_t hipEventQuery(hipEvent_t);
 hipError_t hipEventElapsedTime(float *, hipEvent_t, hipEvent_t);
 hipError_t hipEventDestroy(hipEvent_t);
 hipError_t hipGetLastError();
+hipError_t hipRuntimeGetVersion(int *);
 const char *hipGetErrorString(hipError_t);
 
 // Append a command to a stream (the simulated kernels use it).

@@ -10,6 +10,8 @@
 #include <cstdio>
 #include <cstdlib>
 #include <random>
+#include <string>
+#include <unistd.h>
 #include <vector>
 
 #include "internal.h"
@@ -98,6 +100,61 @@ static void check_plan(const perm_ctx *ctx, const std::vector<MatIn> &in, const 
     (void)ctx;
 }
 
+// The tuning file is keyed by device architecture and HIP runtime version:
+// a saved table loads back; a table for another architecture or runtime,
+// one without the key lines, or one with an F_p chunk above 2^20 or a
+// malformed line is refused and leaves the context's table unchanged.
+static void check_tune_files(perm_ctx *ctx)
+{
+    char path[] = "/tmp/plan_driver_tuneXXXXXX";
+    const int fd = mkstemp(path);
+    CHECK(fd >= 0, "mkstemp");
+    if (fd < 0) return;
+    close(fd);
+    perm_tune t{11, 2};
+    CHECK(perm_tune_set(ctx, PERM_C128, 21, &t) == PERM_OK, "set");
+    CHECK(perm_tune_save(ctx, path) == PERM_OK, "save");
+    ctx->tune.clear();
+    CHECK(perm_tune_load(ctx, path) == PERM_OK, "load of a saved table");
+    perm_tune got{};
+    perm_tune_get(ctx, PERM_C128, 21, &got);
+    CHECK(got.log2_chunk == 11 && got.grid_per_cu == 2, "round trip");
+    std::string text;
+    {
+        FILE *f = fopen(path, "r");
+        char buf[512];
+        while (f && fgets(buf, sizeof buf, f)) text += buf;
+        if (f) fclose(f);
+    }
+    auto write = [&](const std::string &body) {
+        FILE *f = fopen(path, "w");
+        fputs(body.c_str(), f);
+        fclose(f);
+    };
+    auto replace = [&](const std::string &from, const std::string &to) {
+        std::string b = text;
+        const size_t at = b.find(from);
+        CHECK(at != std::string::npos, "%s not in the saved table", from.c_str());
+        if (at != std::string::npos) b.replace(at, from.size(), to);
+        return b;
+    };
+    const std::string arch_line = "# arch " + ctx->arch + "\n";
+    const std::vector<std::string> refused = {
+        replace(arch_line, "# arch gfx942\n"),                 // another architecture
+        replace("# hip 70200000\n", "# hip 60400000\n"),      // another runtime
+        replace(arch_line, ""),                                 // no key
+        text + "2 40 21 0\n",                                   // F_p chunk above 2^20
+        text + "1 20 11\n",                                     // malformed
+    };
+    for (size_t i = 0; i < refused.size(); ++i) {
+        write(refused[i]);
+        CHECK(perm_tune_load(ctx, path) == PERM_EINVAL, "tuning file %zu was accepted", i);
+        perm_tune_get(ctx, PERM_C128, 21, &got);
+        CHECK(got.log2_chunk == 11, "a refused file changed the table");
+    }
+    unlink(path);
+}
+
 int main()
 {
     perm_ctx *ctx = nullptr;
@@ -150,6 +207,7 @@ int main()
     in[1].src_off += 4;
     plan(ctx, in, pl);
     CHECK(ctx->plan_id != id, "changed input reused the plan");
+    check_tune_files(ctx);
     perm_ctx_destroy(ctx);
     printf("planner checks: %d failures\n", failures);
     fflush(stdout);

@@ -243,4 +243,9 @@ hipError_t hipEventElapsedTime(float *ms, hipEvent_t a, hipEvent_t b)
 }
 hipError_t hipEventDestroy(hipEvent_t) { return hipSuccess; }
 hipError_t hipGetLastError() { return hipSuccess; }
+hipError_t hipRuntimeGetVersion(int *v)
+{
+    *v = 70200000;
+    return hipSuccess;
+}
 const char *hipGetErrorString(hipError_t) { return "simulated runtime error"; }

@@ -72,6 +72,39 @@ def test_crt_lift_matches_textbook(P, oracle_lib):
     assert M > 0
 
 
+@pytest.mark.parametrize("n", [9, 11, 13, 15])
+def test_residue_flip_names_the_bad_prime(P, oracle_lib, n):
+    """perm(S_n) for odd n over the sufficient primes plus one redundant
+    prime, residues from the oracle: consistent residues lift to the exact
+    value with no bad prime; one corrupted residue (any of the k + 1, any
+    nonzero offset) is named and the value still comes out right; two
+    corrupted residues are reported as inconsistent."""
+    O = oracle_lib
+    primes = P.perm_schur_primes(n, extra=1)
+    bound = (n / 2) * math.log2(n)
+    res = [O.native.ryser_modp(O.crt.schur_residues(n, p), p) for p in primes]
+    want = O.crt.crt_lift(res, primes)
+    if n <= 10:
+        assert want == O.crt.schur_perm_exact(n)
+    assert want != 0
+    assert P.perm_crt_check(res, primes, bound) == (want, None)
+    g = random.Random(n)
+    for j in range(len(primes)):
+        for _ in range(3):
+            bad = list(res)
+            bad[j] = (bad[j] + g.randrange(1, primes[j])) % primes[j]
+            assert P.perm_crt_check(bad, primes, bound) == (want, j)
+    two = list(res)
+    two[0] = (two[0] + 1) % primes[0]
+    two[-1] = (two[-1] + 7) % primes[-1]
+    with pytest.raises(P.PermError) as e:
+        P.perm_crt_check(two, primes, bound)
+    assert e.value.status == P.PERM_ERANGE
+    with pytest.raises(P.PermError) as e:                 # no redundant prime
+        P.perm_crt_check(res[:-1], primes[:-1], bound * 1.9)
+    assert e.value.status == P.PERM_ERANGE
+
+
 def test_crt_lift_rejects_bad_input(P):
     ps = [1073742209, 1073742517]
     with pytest.raises(P.PermError) as e:
