@@ -26,7 +26,7 @@ Geodesics from I to the n-cycle C_n, (C_n)_{ij} = [i = j+1 mod n] (Sec. 4.1):
   (n (e^{2 pi i (l - j + t)/n} - 1)).
 
 Geodesic from I to the unitary DFT matrix F_n = (w^{jk} / sqrt n),
-w = e^{2 pi i / n} (Sec. 4.3): ``dft_geodesic``.  F_n^4 = I, so its
+w = e^{2 pi i / n} (Sec. 4.2): ``dft_geodesic``.  F_n^4 = I, so its
 eigenvalues lie in {1, i, -1, -i} and P_lam = (1/4) sum_k lam^{-k} F_n^k
 projects onto the eigenspace of lam.  gamma(t) = sum_lam e^{t log lam} P_lam
 with log 1 = 0, log(+-i) = +-i pi/2 and log(-1) = branch * i pi: the paper

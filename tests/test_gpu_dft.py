@@ -1,4 +1,4 @@
-"""DFT geodesic gamma(t) = exp(t log F_n) (paper Sec. 4.3) through the
+"""DFT geodesic gamma(t) = exp(t log F_n) (paper Sec. 4.2) through the
 batched c128 path: oracle parity along the path for both logarithms of -1,
 and the recovery ratio r(n) = |perm F_n| / min_t |perm gamma(t)| equal to
 the oracle's."""
