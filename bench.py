@@ -5,9 +5,16 @@ permanent of the Schur matrix S_28 by CRT over the three smallest 31-bit
 primes p = 1 (mod 28) -- per prime the residue matrix (g^{jk} mod p) already
 resident in HBM, then stage, Gray-code walk over 2^27 Glynn terms, fixed-order
 reduction and 2^-(27) scaling on the device, then the Garner lift on the host.
-Throughput is Glynn subset-terms per second (2^(n-1) per permanent).
+Throughput is Glynn subset-terms per second (2^(n-1) per permanent).  The
+same line carries, under "configs", one sub-record per other workload of the
+metric: a single 14x14 Haar unitary (latency), 50,000 Haar U(20) and O(20)
+in one launch each, 10,000 ragged Gaussian matrices, and the serving stream
+(p50/p99 per class at 0.5/0.7/0.9 of saturation); each with the median of
+at least five timed launches, the walk kernel's roofline and the oracle's
+CPU baseline.
 
-Other workloads (--workload): single14 (one 14x14 Haar unitary, c128),
+Single workloads (--workload): schur28 (the S_28 line alone), single14 (one
+14x14 Haar unitary, c128),
 haar20 (50,000 Haar U(20) c128 and 50,000 Haar O(20) f64 in one persistent
 launch each), ragged (10,000 GUE/GOE/real and complex Ginibre matrices,
 n uniform in 8..24, one fused launch), serve (Poisson-arrival geodesic and
@@ -112,11 +119,45 @@ def roofline(ops_per_launch, walk_ms, launches, traffic=None, flops_ratio=None):
 
 
 # ---------------------------------------------------------------- CPU baseline
+def host_info():
+    """The host the oracle ran on: logical CPUs, CPUs this process may use,
+    and the CPU model (as lscpu prints it, from /proc/cpuinfo)."""
+    info = {"nproc": os.cpu_count()}
+    try:
+        info["affinity_cpus"] = len(os.sched_getaffinity(0))
+    except (AttributeError, OSError):
+        pass
+    try:
+        with open("/proc/cpuinfo") as f:
+            for line in f:
+                if line.startswith("model name"):
+                    info["cpu_model"] = line.split(":", 1)[1].strip()
+                    break
+    except OSError:
+        pass
+    return info
+
+
+def _with_host(d):
+    """Add the host description and an all-core figure: the one-thread rate
+    times nproc, i.e. linear scaling, an estimate (the oracle runs on the
+    16 threads of one GPU's host share, never on every core of the box)."""
+    h = host_info()
+    d.update(h)
+    if d.get("value_1thread") and h.get("nproc"):
+        d["all_cores_linear_estimate"] = d["value_1thread"] * h["nproc"]
+    return d
+
+
+def _threads():
+    return min(HOST_THREADS, os.cpu_count() or 1)
+
+
 def cpu_baseline_schur(n, primes, seconds=12.0):
     """Oracle Ryser mod p on S_n, bounded prefix, all host threads."""
     from oracle import crt, native
     mats = [crt.schur_residues(n, p) for p in primes]
-    threads = min(HOST_THREADS, os.cpu_count() or 1)
+    threads = _threads()
     # calibrate one thread on a short prefix
     t = time.perf_counter()
     native.ryser_modp_prefix(mats[0], primes[0], 1 << 18)
@@ -138,41 +179,164 @@ def cpu_baseline_schur(n, primes, seconds=12.0):
     ryser_subsets_per_s = sum(done) / dt
     # one permanent = 2^n Ryser subsets on the CPU = 2^(n-1) Glynn terms in the metric
     value = ryser_subsets_per_s / (1 << n) * (1 << (n - 1))
-    return {"value": value, "unit": "subset-terms/s (Glynn-term equivalents)", "cores": threads,
-            "kind": "oracle", "value_1thread": rate1 / 2,
-            "sample": f"oracle Ryser mod p on S_{n}: first {per_thread - 1} of 2^{n} subsets per "
-                      f"thread, {threads} threads in {dt:.1f} s; rate scaled to 2^{n - 1} terms "
-                      f"per permanent"}
+    return _with_host({
+        "value": value, "unit": "subset-terms/s (Glynn-term equivalents)", "cores": threads,
+        "kind": "oracle", "value_1thread": rate1 / 2,
+        "sample": f"oracle Ryser mod p on S_{n}: first {per_thread - 1} of 2^{n} subsets per "
+                  f"thread, {threads} threads in {dt:.1f} s; rate scaled to 2^{n - 1} terms "
+                  f"per permanent"})
 
 
-def cpu_baseline_many(mats, field, seconds=10.0):
+def _oracle_perm(A, field):
     from oracle import native
-    threads = min(HOST_THREADS, os.cpu_count() or 1)
-    t = time.perf_counter()
-    native.ryser_many(mats[:2])
-    per = (time.perf_counter() - t) / 2
-    k = max(1, min(len(mats) // threads, int(seconds / max(per, 1e-9))))
-    done = []
+    return native.ryser_c128(A) if field == "c128" else native.ryser_f64(A)
 
-    def work(i):
-        native.ryser_many(mats[i * k:(i + 1) * k])
-        done.append(k)
 
+def cpu_baseline_many(mats, field, seconds=5.0, label=None):
+    """The oracle on the matrices of a batch, one whole matrix per host
+    thread at a time, threads taking the next matrix of a seeded random order
+    until `seconds` have passed; every matrix started is finished and
+    counted.  mats: list of (A, field) or arrays of one field."""
+    import queue
+    mats = [m if isinstance(m, tuple) else (m, field) for m in mats]
+    order = np.random.Generator(np.random.PCG64(7)).permutation(len(mats))
+    threads = _threads()
+    # one thread, a few matrices: the per-core rate
     t = time.perf_counter()
-    ths = [threading.Thread(target=work, args=(i,)) for i in range(threads)]
+    k1 = 0
+    while k1 < len(mats) and (k1 < 2 or time.perf_counter() - t < 0.5):
+        _oracle_perm(*mats[order[k1]])
+        k1 += 1
+    rate1 = k1 / (time.perf_counter() - t)
+    q = queue.SimpleQueue()
+    for i in order:
+        q.put(int(i))
+    done = [0] * threads
+    t0 = time.perf_counter()
+
+    def work(w):
+        while time.perf_counter() - t0 < seconds:
+            try:
+                i = q.get_nowait()
+            except queue.Empty:
+                return
+            _oracle_perm(*mats[i])
+            done[w] += 1
+
+    ths = [threading.Thread(target=work, args=(w,)) for w in range(threads)]
     for th in ths:
         th.start()
     for th in ths:
         th.join()
-    dt = time.perf_counter() - t
-    return {"value": sum(done) / dt, "unit": "perms/s", "cores": threads, "kind": "oracle",
-            "value_1thread": 1.0 / per,
-            "sample": f"oracle Ryser on {sum(done)} of the {field} matrices ({threads} threads, "
-                      f"{dt:.1f} s)"}
+    dt = time.perf_counter() - t0
+    return _with_host({
+        "value": sum(done) / dt, "unit": "perms/s", "cores": threads, "kind": "oracle",
+        "value_1thread": rate1,
+        "sample": f"oracle Ryser on {sum(done)} of the {len(mats)} {label or field} matrices "
+                  f"(seeded random order, {threads} threads, {dt:.1f} s)"})
+
+
+def cpu_baseline_single(A, seconds=2.0):
+    """One matrix: the oracle's latency on one thread (median of 5 groups)
+    and its throughput with every host thread computing the same matrix."""
+    from oracle import native
+    t = time.perf_counter()
+    native.ryser_c128(A)
+    once = time.perf_counter() - t
+    per = max(1, int(0.1 / max(once, 1e-9)))
+    groups = []
+    for _ in range(5):
+        t = time.perf_counter()
+        for _ in range(per):
+            native.ryser_c128(A)
+        groups.append((time.perf_counter() - t) / per)
+    lat = float(np.median(groups))
+    threads = _threads()
+    counts = [0] * threads
+    t0 = time.perf_counter()
+
+    def work(w):
+        while time.perf_counter() - t0 < seconds:
+            native.ryser_c128(A)
+            counts[w] += 1
+
+    ths = [threading.Thread(target=work, args=(w,)) for w in range(threads)]
+    for th in ths:
+        th.start()
+    for th in ths:
+        th.join()
+    dt = time.perf_counter() - t0
+    return _with_host({
+        "value": sum(counts) / dt, "unit": "perms/s", "cores": threads, "kind": "oracle",
+        "value_1thread": 1.0 / lat, "us_per_call_1thread": lat * 1e6,
+        "sample": f"oracle Ryser on the same matrix: 5 x {per} calls on one thread, then "
+                  f"{sum(counts)} calls on {threads} threads in {dt:.1f} s"})
+
+
+def cpu_baseline_serve(P, reqs, seconds_schur=2.0):
+    """The oracle on the serving stream, in the stream's unit (Glynn-term
+    equivalents per second), from a sample: 16 geodesic points per order (of
+    64), and for each Schur order a Ryser prefix of S_n on every thread.
+    The time of the whole stream on the host threads is extrapolated from
+    the sample (per-order mean time x count), and stated as such."""
+    from oracle import native
+    threads = _threads()
+    total_s = 0.0
+    notes = []
+    import concurrent.futures as cf
+    for n in range(11, 26, 2):
+        pts = [r[0] for r in reqs if r[3] == "geodesic" and r[4] == n][:16]
+        t = time.perf_counter()
+        with cf.ThreadPoolExecutor(threads) as ex:
+            list(ex.map(native.ryser_c128, pts))
+        dt = time.perf_counter() - t
+        cnt = sum(1 for r in reqs if r[3] == "geodesic" and r[4] == n)
+        total_s += dt * cnt / len(pts)
+        notes.append(f"n={n}: {len(pts)} pts in {dt:.2f} s")
+    for n in sorted({r[4] for r in reqs if r[3] == "schur"}):
+        rs = [r for r in reqs if r[3] == "schur" and r[4] == n]
+        A, _, p = rs[0][0], rs[0][1], rs[0][2]
+        t = time.perf_counter()
+        native.ryser_modp_prefix(A, p, 1 << 18)
+        rate1 = (1 << 18) / (time.perf_counter() - t)
+        per = int(max(1 << 18, rate1 * seconds_schur))
+        t = time.perf_counter()
+        with cf.ThreadPoolExecutor(threads) as ex:
+            list(ex.map(lambda i: native.ryser_modp_prefix(A, p, per), range(threads)))
+        dt = time.perf_counter() - t
+        rate = threads * (per - 1) / dt                 # Ryser subsets per second
+        total_s += len(rs) * (1 << n) / rate
+        notes.append(f"S_{n}: {per - 1} subsets x {threads} threads in {dt:.2f} s")
+    terms = sum(1 << (r[0].shape[0] - 1) for r in reqs)
+    return _with_host({
+        "value": terms / total_s, "unit": "subset-terms/s (Glynn-term equivalents)",
+        "cores": threads, "kind": "oracle", "extrapolated": True,
+        "stream_seconds_estimate": total_s,
+        "sample": "oracle on a sample of the serving stream, whole-stream time extrapolated: " +
+                  "; ".join(notes)})
+
+
+def median_launches(fn, reps):
+    """fn() `reps` times, each followed by a device synchronisation; the
+    wall time of each (seconds)."""
+    ts = []
+    for _ in range(reps):
+        t0 = time.perf_counter()
+        fn()
+        sync()
+        ts.append(time.perf_counter() - t0)
+    return ts
+
+
+def progress(msg):
+    print(msg, file=sys.stderr, flush=True)
 
 
 # ------------------------------------------------------------------ workloads
 def bench_schur(P, ctx, args):
+    """S_28 over its three primes; each step is one synchronous perm_crt_int
+    (residues back on the host, CRT lift), so a step's host time is its
+    duration."""
     import torch
     n = 28
     primes = P.perm_schur_primes(n)
@@ -185,9 +349,12 @@ def bench_schur(P, ctx, args):
     sync()
     P.perm_prof_enable(ctx, True)
     P.perm_prof_read(ctx)
+    steps_s = []
     t0 = time.perf_counter()
     for _ in range(args.steps):
+        ts = time.perf_counter()
         val, res = P.perm_crt_int(ctx, mats, primes, bound, flags=flags)
+        steps_s.append(time.perf_counter() - ts)
     sync()
     dt = time.perf_counter() - t0
     walk_ms, launches = P.perm_prof_read(ctx)
@@ -197,6 +364,7 @@ def bench_schur(P, ctx, args):
     line = {
         "metric": METRIC, "value": terms * args.steps / dt, "unit": "subset-terms/s",
         "ms_per_step": dt / args.steps * 1e3, "dtype": "f64",
+        "median_ms_per_step": float(np.median(steps_s)) * 1e3,
         "config": {"workload": "schur_S28_crt_3primes", "n": n, "primes": primes,
                    "field": ("F_p (32-bit Montgomery walk)" if args.montgomery
                              else "F_p (exact FP64 Barrett walk)") + " + CRT",
@@ -213,81 +381,120 @@ def bench_schur(P, ctx, args):
     return line
 
 
-def bench_single14(P, ctx, args):
+def sub_single14(P, ctx, args, calls=200, groups=5):
+    """Config 1: one 14x14 Haar unitary per call, device pointers, result
+    left on the device; median per-call time over `groups` groups of
+    `calls` back-to-back calls.  Timing events add about 9 us to a call, so
+    the kernel duration comes from a second, profiled pass."""
     import torch
     from paper_2602_10141_amd import ensembles as E
-    U = torch.from_numpy(E.haar_unitary(14, E.rng(1, 0))).cuda()
-    for _ in range(args.warmup):
-        out = P.perm_c128(ctx, U)
+    A = E.haar_unitary(14, E.rng(1, 0))
+    U = torch.from_numpy(A).cuda()
+    for _ in range(20):
+        P.perm_c128(ctx, U)
     sync()
-    # Recording the per-launch timing events adds about 9 us to each call on
-    # the stream, half a call, so the value is timed without them and the
-    # kernel duration comes from a second, profiled pass of the same calls.
-    t0 = time.perf_counter()
-    for _ in range(args.steps):
-        out = P.perm_c128(ctx, U)
-    sync()
-    dt = time.perf_counter() - t0
+    per_call = []
+    for _ in range(groups):
+        t0 = time.perf_counter()
+        for _ in range(calls):
+            P.perm_c128(ctx, U)
+        sync()
+        per_call.append((time.perf_counter() - t0) / calls)
     P.perm_prof_enable(ctx, True)
     P.perm_prof_read(ctx)
-    t1 = time.perf_counter()
-    for _ in range(args.steps):
-        out = P.perm_c128(ctx, U)
+    for _ in range(calls):
+        P.perm_c128(ctx, U)
     sync()
-    dt_prof = time.perf_counter() - t1
     walk_ms, launches = P.perm_prof_read(ctx)
     P.perm_prof_enable(ctx, False)
-    terms = 1 << 13
-    return {"metric": METRIC, "value": args.steps / dt, "unit": "perms/s",
-            "ms_per_step": dt / args.steps * 1e3, "dtype": "f64",
-            "config": {"workload": "haar_unitary_14_c128", "n": 14},
-            "profiled_ms_per_step": dt_prof / args.steps * 1e3,
-            "roofline": roofline(terms * ops_per_term("c128", 14), walk_ms, launches)}
+    med = float(np.median(per_call))
+    # the same call through perm_c128_noalloc (static scratch, no allocation)
+    out = torch.empty(2, dtype=torch.float64, device="cuda")
+    na = []
+    for _ in range(groups):
+        t0 = time.perf_counter()
+        for _ in range(calls):
+            P.perm_c128_noalloc(ctx, U, out=out)
+        sync()
+        na.append((time.perf_counter() - t0) / calls)
+    rec = {"workload": "haar_unitary_14_c128", "n": 14, "value": 1.0 / med, "unit": "perms/s",
+           "us_per_call_median": med * 1e6, "timed": f"{groups} groups of {calls} calls",
+           "noalloc_us_per_call_median": float(np.median(na)) * 1e6, "dtype": "c128",
+           "roofline": roofline((1 << 13) * ops_per_term("c128", 14), walk_ms, launches, None,
+                                flops_per_op("c128", 14))}
+    if not args.no_cpu:
+        rec["cpu_baseline"] = cpu_baseline_single(A)
+    return rec
+
+
+def sub_batch(P, ctx, args, workload, mats, reps=5, cpu_label=None):
+    """Configs 3 and 4: one perm_batch of all `mats` ((A, field, p) triples),
+    inputs resident in HBM, results left on the device; one warm-up launch,
+    then the median of `reps` timed launches."""
+    import torch
+    items, data = P.pack_matrices(mats)
+    d = torch.from_numpy(data).cuda()
+    res = torch.zeros((len(mats), 2), dtype=torch.float64, device="cuda")
+    fn = lambda: P.perm_batch(ctx, items, d, out=res)    # noqa: E731
+    fn()
+    sync()
+    P.perm_prof_enable(ctx, True)
+    P.perm_prof_read(ctx)
+    ts = median_launches(fn, max(5, reps))
+    walk_ms, launches = P.perm_prof_read(ctx)
+    P.perm_prof_enable(ctx, False)
+    med = float(np.median(ts))
+    ns = [m[0].shape[0] for m in mats]
+    fields = sorted({m[1] for m in mats})
+    terms = sum(1 << (k - 1) for k in ns)
+    ops = sum((1 << (m[0].shape[0] - 1)) * ops_per_term(m[1], m[0].shape[0]) for m in mats)
+    flops = sum((1 << (m[0].shape[0] - 1)) * ops_per_term(m[1], m[0].shape[0]) *
+                flops_per_op(m[1], m[0].shape[0]) for m in mats)
+    rec = {"workload": workload, "count": len(mats), "value": len(mats) / med, "unit": "perms/s",
+           "median_ms": med * 1e3, "timed_launches": len(ts),
+           "launch_ms": [round(t * 1e3, 3) for t in ts], "terms_per_s": terms / med,
+           "dtype": "+".join(fields),
+           "roofline": roofline(ops * len(ts) / max(launches, 1), walk_ms, launches, None,
+                                flops / ops)}
+    if not args.no_compare:
+        one = per_matrix_launches(P, ctx, items, d, 2000)
+        one["batched_speedup"] = rec["value"] / one["perms_per_s"]
+        rec["one_launch_per_matrix"] = one
+        t0 = time.perf_counter()
+        P.perm_batch(ctx, items, data)
+        rec["host_buffers_perms_per_s"] = len(mats) / (time.perf_counter() - t0)
+    if not args.no_cpu:
+        rec["cpu_baseline"] = cpu_baseline_many([(m[0], m[1]) for m in mats], None,
+                                                label=cpu_label or workload)
+    return rec
+
+
+def bench_single14(P, ctx, args):
+    rec = sub_single14(P, ctx, args)
+    return {"metric": METRIC, "value": rec["value"], "unit": "perms/s",
+            "ms_per_step": rec["us_per_call_median"] * 1e-3, "dtype": "c128",
+            "config": {"workload": rec["workload"], "n": 14}, "roofline": rec["roofline"],
+            **({"cpu_baseline": rec["cpu_baseline"]} if "cpu_baseline" in rec else {}),
+            "detail": rec}
+
+
+def haar20_inputs(count):
+    from paper_2602_10141_amd import ensembles as E
+    U = E.haar_unitary(20, E.rng(3, 0), count=count)
+    O = E.haar_orthogonal(20, E.rng(3, 1), count=count)
+    return U, O
 
 
 def bench_haar20(P, ctx, args):
-    import torch
-    from paper_2602_10141_amd import ensembles as E
-    n, count = 20, args.count
-    U = E.haar_unitary(n, E.rng(3, 0), count=count)
-    O = E.haar_orthogonal(n, E.rng(3, 1), count=count)
-    out = {}
-    for name, M, field in (("c128", U, "c128"), ("f64", O, "f64")):
-        items, data = P.pack_matrices([(m, field, 0) for m in M])
-        d = torch.from_numpy(data).cuda()
-        res = torch.zeros((count, 2), dtype=torch.float64, device="cuda")
-        for _ in range(max(1, args.warmup)):
-            P.perm_batch(ctx, items, d, out=res)
-        sync()
-        P.perm_prof_enable(ctx, True)
-        P.perm_prof_read(ctx)
-        t0 = time.perf_counter()
-        steps = max(1, args.steps // 20)
-        for _ in range(steps):
-            P.perm_batch(ctx, items, d, out=res)
-        sync()
-        dt = (time.perf_counter() - t0) / steps
-        walk_ms, launches = P.perm_prof_read(ctx)
-        P.perm_prof_enable(ctx, False)
-        terms = count * (1 << (n - 1))
-        out[name] = {"perms_per_s": count / dt, "terms_per_s": terms / dt, "ms": dt * 1e3,
-                     "roofline": roofline(terms * ops_per_term(field, n), walk_ms, launches,
-                                          None, flops_per_op(field, n))}
-        if not args.no_compare:
-            one = per_matrix_launches(P, ctx, items, d, 2000)
-            one["batched_speedup"] = out[name]["perms_per_s"] / one["perms_per_s"]
-            out[name]["one_launch_per_matrix"] = one
-            # the same batch handed over in host memory: PCIe copy in and out
-            # included (context only, never the reported value)
-            t0 = time.perf_counter()
-            P.perm_batch(ctx, items, data)
-            out[name]["host_buffers_perms_per_s"] = count / (time.perf_counter() - t0)
-    line = {"metric": METRIC, "value": out["c128"]["terms_per_s"], "unit": "subset-terms/s",
-            "ms_per_step": out["c128"]["ms"] + out["f64"]["ms"], "dtype": "f64",
-            "config": {"workload": "haar20_batched", "count": count, "n": n},
+    U, O = haar20_inputs(args.count)
+    out = {"c128": sub_batch(P, ctx, args, "haar_unitary_20_c128", [(m, "c128", 0) for m in U]),
+           "f64": sub_batch(P, ctx, args, "haar_orthogonal_20_f64", [(m, "f64", 0) for m in O])}
+    line = {"metric": METRIC, "value": out["c128"]["value"], "unit": "perms/s",
+            "ms_per_step": out["c128"]["median_ms"] + out["f64"]["median_ms"], "dtype": "c128",
+            "config": {"workload": "haar20_batched", "count": args.count, "n": 20},
             "roofline": out["c128"]["roofline"], "detail": out}
-    if not args.no_cpu:
-        line["cpu_baseline"] = cpu_baseline_many(U[:4000], "Haar U(20) c128")
+    if "cpu_baseline" in out["c128"]:
+        line["cpu_baseline"] = out["c128"]["cpu_baseline"]
     return line
 
 
@@ -363,34 +570,14 @@ def ragged_inputs(count, seed=4):
 
 
 def bench_ragged(P, ctx, args):
-    import torch
-    mats = ragged_inputs(args.count)
-    items, data = P.pack_matrices(mats)
-    d = torch.from_numpy(data).cuda()
-    res = torch.zeros((len(mats), 2), dtype=torch.float64, device="cuda")
-    for _ in range(max(1, args.warmup)):
-        P.perm_batch(ctx, items, d, out=res)
-    sync()
-    P.perm_prof_enable(ctx, True)
-    P.perm_prof_read(ctx)
-    steps = max(1, args.steps // 20)
-    t0 = time.perf_counter()
-    for _ in range(steps):
-        P.perm_batch(ctx, items, d, out=res)
-    sync()
-    dt = (time.perf_counter() - t0) / steps
-    walk_ms, launches = P.perm_prof_read(ctx)
-    P.perm_prof_enable(ctx, False)
-    terms = sum(1 << (m[0].shape[0] - 1) for m in mats)
-    ops = sum((1 << (m[0].shape[0] - 1)) * ops_per_term(m[1], m[0].shape[0]) for m in mats)
-    line = {"metric": METRIC, "value": len(mats) / dt, "unit": "perms/s", "ms_per_step": dt * 1e3,
-            "dtype": "f64", "config": {"workload": "ragged_gaussian_n8_24", "count": len(mats),
-                                       "terms": terms},
-            "roofline": roofline(ops, walk_ms, launches)}
-    if not args.no_compare:
-        one = per_matrix_launches(P, ctx, items, d, 2000)
-        one["batched_speedup"] = len(mats) / dt / one["perms_per_s"]
-        line["one_launch_per_matrix"] = one
+    rec = sub_batch(P, ctx, args, "ragged_gaussian_n8_24", ragged_inputs(args.count),
+                    cpu_label="ragged GUE/GOE/Ginibre")
+    line = {"metric": METRIC, "value": rec["value"], "unit": "perms/s",
+            "ms_per_step": rec["median_ms"], "dtype": rec["dtype"],
+            "config": {"workload": rec["workload"], "count": rec["count"]},
+            "roofline": rec["roofline"], "detail": rec}
+    if "cpu_baseline" in rec:
+        line["cpu_baseline"] = rec["cpu_baseline"]
     return line
 
 
@@ -478,42 +665,107 @@ def _pcts(x):
             "mean_us": float(np.mean(x)), "count": int(len(x))}
 
 
-def bench_serve(P, ctx, args):
+SERVE_EVENT_PAIRS = 16384
+
+
+def sub_serve(P, ctx, args, loads=(0.5, 0.7, 0.9)):
+    """Config 5: the 530-request stream through the request loop, all at
+    once (saturation) and with Poisson arrivals at fractions of the
+    saturation rate; latency from submit to the result on the host, p50/p99
+    per class.  The walk launches of the saturation run are timed with HIP
+    events on the server's streams; two slices overlap on the device, so the
+    summed launch durations exceed the busy time and the fraction is a lower
+    bound."""
     reqs = serve_requests(P)
     serve_tuning(P, ctx)
-    terms = sum(1 << (r[0].shape[0] - 1) for r in reqs)
-    slice_us = args.slice_us
-    _serve_run(P, ctx, reqs[:40], None, 0, slice_us)                 # warm-up
-    vals, lats, wall, st = _serve_run(P, ctx, reqs, None, 1, slice_us)
-    sat_rate = len(reqs) / wall
-    cls = np.array([r[3] for r in reqs])
-    result = {"saturation": {"wall_s": wall, "requests_per_s": sat_rate,
-                             "terms_per_s": terms / wall, **_pcts(lats),
-                             "slices": st["slices"], "busy_s": st["busy_s"],
-                             "items": st["items"], "rate": st["rate"],
-                             "geodesic": _pcts(lats[cls == "geodesic"]),
-                             "schur": _pcts(lats[cls == "schur"])}}
-    ref = vals
-    for f in (0.5, 0.7, 0.9):
-        v, l, w, s2 = _serve_run(P, ctx, reqs, f * sat_rate, 2 + int(f * 10), slice_us)
-        assert v == ref, "served results differ between runs"
-        result[f"load_{f}"] = {"wall_s": w, "offered_per_s": f * sat_rate, **_pcts(l),
-                               "slices": s2["slices"], "busy_s": s2["busy_s"],
-                               "items": s2["items"], "rate": s2["rate"],
-                               "geodesic": _pcts(l[cls == "geodesic"]),
-                               "schur": _pcts(l[cls == "schur"])}
-    # every Schur residue is 0 for even n; geodesic perms are real and |.| <= 1
-    for r, v in zip(reqs, ref):
-        if r[3] == "schur":
-            assert v == 0
-        else:
-            assert abs(v.imag) < 1e-12 and abs(v) <= 1 + 1e-12
-    return {"metric": METRIC, "value": terms / wall, "unit": "subset-terms/s",
-            "ms_per_step": wall * 1e3, "dtype": "f64",
-            "config": {"workload": "serve_geodesic_c128_and_schur_modp", "requests": len(reqs),
-                       "terms": terms, "slice_us": slice_us,
+    try:
+        terms = sum(1 << (r[0].shape[0] - 1) for r in reqs)
+        ops = sum((1 << (r[0].shape[0] - 1)) * ops_per_term(r[1], r[0].shape[0]) for r in reqs)
+        flops = sum((1 << (r[0].shape[0] - 1)) * ops_per_term(r[1], r[0].shape[0]) *
+                    flops_per_op(r[1], r[0].shape[0]) for r in reqs)
+        slice_us = args.slice_us
+        _serve_run(P, ctx, reqs[:40], None, 0, slice_us)                 # warm-up
+        P.perm_prof_enable(ctx, SERVE_EVENT_PAIRS)
+        P.perm_prof_read(ctx)
+        vals, lats, wall, st = _serve_run(P, ctx, reqs, None, 1, slice_us)
+        walk_ms, launches = P.perm_prof_read(ctx)
+        P.perm_prof_enable(ctx, False)
+        sat_rate = len(reqs) / wall
+        cls = np.array([r[3] for r in reqs])
+        rf = roofline(ops / max(launches, 1), walk_ms, launches, None, flops / ops)
+        rf["all_launches_timed"] = launches < SERVE_EVENT_PAIRS
+        rf["busy_frac"] = round(ops / max(st["busy_s"], 1e-9) / PEAK_LANE_OPS, 4)
+        result = {"saturation": {"wall_s": wall, "requests_per_s": sat_rate,
+                                 "terms_per_s": terms / wall, **_pcts(lats),
+                                 "slices": st["slices"], "busy_s": st["busy_s"],
+                                 "items": st["items"], "rate": st["rate"],
+                                 "geodesic": _pcts(lats[cls == "geodesic"]),
+                                 "schur": _pcts(lats[cls == "schur"])}}
+        ref = vals
+        for f in loads:
+            progress(f"serve: load {f}")
+            v, l, w, s2 = _serve_run(P, ctx, reqs, f * sat_rate, 2 + int(f * 10), slice_us)
+            assert v == ref, "served results differ between runs"
+            result[f"load_{f}"] = {"wall_s": w, "offered_per_s": f * sat_rate, **_pcts(l),
+                                   "slices": s2["slices"], "busy_s": s2["busy_s"],
+                                   "items": s2["items"], "rate": s2["rate"],
+                                   "geodesic": _pcts(l[cls == "geodesic"]),
+                                   "schur": _pcts(l[cls == "schur"])}
+        # every Schur residue is 0 for even n; geodesic perms are real and |.| <= 1
+        for r, v in zip(reqs, ref):
+            if r[3] == "schur":
+                assert v == 0
+            else:
+                assert abs(v.imag) < 1e-12 and abs(v) <= 1 + 1e-12
+    finally:
+        serve_tuning(P, ctx, on=False)
+    rec = {"workload": "serve_geodesic_c128_and_schur_modp", "requests": len(reqs),
+           "value": terms / wall, "unit": "subset-terms/s", "terms": terms,
+           "slice_us": slice_us, "c128_log2_chunk_max": SERVE_FLOAT_CHUNK, "dtype": "c128+f64",
+           "roofline": rf, "latency": result}
+    if not args.no_cpu:
+        rec["cpu_baseline"] = cpu_baseline_serve(P, reqs)
+    return rec
+
+
+def bench_serve(P, ctx, args):
+    rec = sub_serve(P, ctx, args)
+    line = {"metric": METRIC, "value": rec["value"], "unit": "subset-terms/s",
+            "ms_per_step": rec["latency"]["saturation"]["wall_s"] * 1e3, "dtype": rec["dtype"],
+            "config": {"workload": rec["workload"], "requests": rec["requests"],
+                       "terms": rec["terms"], "slice_us": rec["slice_us"],
                        "c128_log2_chunk_max": SERVE_FLOAT_CHUNK},
-            "latency": result}
+            "roofline": rec["roofline"], "latency": rec["latency"]}
+    if "cpu_baseline" in rec:
+        line["cpu_baseline"] = rec["cpu_baseline"]
+    return line
+
+
+def bench_default(P, ctx, args):
+    """The headline line: S_28 over three primes is `value`; configs 1, 3,
+    4 and 5 follow as sub-records, each with its median, roofline and
+    oracle baseline."""
+    progress("S_28 over three primes")
+    line = bench_schur(P, ctx, args)
+    cfg = {}
+    progress("config 1: one Haar U(14)")
+    cfg["single_haar_u14_c128"] = sub_single14(P, ctx, args)
+    progress("config 3: 50,000 Haar U(20) and O(20)")
+    U, O = haar20_inputs(50000)
+    cfg["haar_u20_c128_50000"] = sub_batch(P, ctx, args, "haar_unitary_20_c128",
+                                           [(m, "c128", 0) for m in U])
+    del U
+    cfg["haar_o20_f64_50000"] = sub_batch(P, ctx, args, "haar_orthogonal_20_f64",
+                                          [(m, "f64", 0) for m in O])
+    del O
+    progress("config 4: 10,000 ragged Gaussian matrices")
+    cfg["ragged_gaussian_10000"] = sub_batch(P, ctx, args, "ragged_gaussian_n8_24",
+                                             ragged_inputs(10000),
+                                             cpu_label="ragged GUE/GOE/Ginibre")
+    progress("config 5: serving stream")
+    cfg["serve_stream_530"] = sub_serve(P, ctx, args)
+    line["configs"] = cfg
+    return line
 
 
 def bench_copycal(P, ctx, args):
@@ -590,7 +842,7 @@ def bench_stats(P, ctx, args):
         row["U"]["stats"], row["O"]["stats"] = haar_statistics(vals["U"], vals["O"], n)
         runs.append(row)
     return {"metric": METRIC, "value": tot_perms / tot_s, "unit": "perms/s",
-            "ms_per_step": tot_s * 1e3, "dtype": "f64",
+            "ms_per_step": tot_s * 1e3, "dtype": "c128+f64",
             "config": {"workload": "haar_U_O_statistics_n7_23", "count": count},
             "runs": runs}
 
@@ -637,14 +889,14 @@ def bench_sizes(P, ctx, args):
         tot_terms += terms
         tot_s += dt
     return {"metric": METRIC, "value": tot_terms / tot_s, "unit": "subset-terms/s",
-            "ms_per_step": tot_s * 1e3, "dtype": "f64",
+            "ms_per_step": tot_s * 1e3, "dtype": "c128+f64+f64(F_p)",
             "config": {"workload": "single_matrix_orders_20_36",
                        "cases": [f"{f}{n}" for f, n in cases]},
             "runs": rows}
 
 
 def bench_dft(P, ctx, args):
-    """The DFT-geodesic fingerprint (paper Sec. 4.3): perm(gamma(t)) on a
+    """The DFT-geodesic fingerprint (paper Sec. 4.2): perm(gamma(t)) on a
     257-point t grid for odd n in 7..23 and both logarithms of -1, one
     batched launch per branch; r(n) = |perm F_n| / min_t |perm gamma(t)|."""
     import torch
@@ -673,7 +925,7 @@ def bench_dft(P, ctx, args):
                          "abs_perm_F": float(a[-1]), "min_abs_perm": float(a[k]),
                          "perm_half": [float(v[i][128].real), float(v[i][128].imag)]})
     return {"metric": METRIC, "value": tot / tot_s, "unit": "perms/s", "ms_per_step": tot_s * 1e3,
-            "dtype": "f64", "config": {"workload": "dft_geodesic_fingerprint", "n": ns,
+            "dtype": "c128", "config": {"workload": "dft_geodesic_fingerprint", "n": ns,
                                        "grid_points": len(grid), "branches": [1, -1]},
             "runs": runs}
 
@@ -711,6 +963,8 @@ def bench_schur_odd(P, ctx, args):
         lifts = {P.perm_crt_lift([res[i] for i in sub], [primes[i] for i in sub], bound)
                  for sub in itertools.combinations(range(len(primes)), k)}
         assert lifts == {val}, f"S_{n}: prime subsets disagree"
+        if len(primes) > k:
+            assert P.perm_crt_check(res, primes, bound) == (val, None), f"S_{n}: a residue is off"
         assert val != 0 and abs(val) <= n ** (n / 2)
         terms = len(primes) * (1 << (n - 1))
         run = {"n": n, "primes": primes, "needed": k, "wall_s": dt, "terms": terms,
@@ -731,7 +985,7 @@ def bench_schur_odd(P, ctx, args):
             "runs": runs}
 
 
-WORKLOADS = {"dft": bench_dft, "stats": bench_stats, "schur_odd": bench_schur_odd, "copycal": bench_copycal, "serve": bench_serve, "schur28": bench_schur, "single14": bench_single14, "haar20": bench_haar20,
+WORKLOADS = {"default": bench_default, "dft": bench_dft, "stats": bench_stats, "schur_odd": bench_schur_odd, "copycal": bench_copycal, "serve": bench_serve, "schur28": bench_schur, "single14": bench_single14, "haar20": bench_haar20,
              "ragged": bench_ragged, "sizes": bench_sizes}
 
 
@@ -740,7 +994,7 @@ def main():
     ap.add_argument("--gpus", type=int, default=1)
     ap.add_argument("--steps", type=int, default=100)
     ap.add_argument("--warmup", type=int, default=10)
-    ap.add_argument("--workload", default="schur28", choices=sorted(WORKLOADS))
+    ap.add_argument("--workload", default="default", choices=sorted(WORKLOADS))
     ap.add_argument("--count", type=int, default=50000)
     ap.add_argument("--no-cpu", action="store_true", help="skip the oracle CPU baseline")
     ap.add_argument("--slice-us", type=float, default=500.0,

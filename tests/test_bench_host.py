@@ -65,3 +65,25 @@ def test_measured_traffic_follows_the_kernel_sources(tmp_path, monkeypatch):
     prof.write_text("source_hash: 0000000000000000\nbytes_per_launch: 12345\n")
     assert bench.measured_traffic("traffic.txt") is None
     assert bench.measured_traffic("no_such_profile.txt") is None
+
+
+def test_cpu_baseline_states_the_host_and_its_sample():
+    """The oracle baseline names its thread count, the host's CPU count and
+    model, and an all-core figure that is labelled as a linear estimate."""
+    from paper_2602_10141_amd import ensembles as E
+    mats = [(E.ginibre_real(8, E.rng(90, i)), "f64") for i in range(40)]
+    r = bench.cpu_baseline_many(mats, None, seconds=0.2, label="test")
+    assert r["kind"] == "oracle" and r["unit"] == "perms/s" and r["value"] > 0
+    assert r["cores"] == min(bench.HOST_THREADS, os.cpu_count())
+    assert r["nproc"] == os.cpu_count() and "cpu_model" in r
+    assert r["all_cores_linear_estimate"] == r["value_1thread"] * r["nproc"]
+    assert "of the 40 test matrices" in r["sample"]
+
+
+def test_default_workload_is_the_headline_with_sub_records():
+    assert bench.WORKLOADS["default"] is bench.bench_default
+    import inspect
+    src = inspect.getsource(bench.bench_default)
+    for key in ("single_haar_u14_c128", "haar_u20_c128_50000", "haar_o20_f64_50000",
+                "ragged_gaussian_10000", "serve_stream_530"):
+        assert key in src
