@@ -186,6 +186,8 @@ int perm_prof_read(perm_ctx *ctx, double *walk_ms, uint64_t *launches);
  * Schur bound of paper Sec. 2.1), plus `extra` more.  *k receives the count.
  * Errors: PERM_EINVAL (n < 1), PERM_ERANGE (max_primes too small). */
 int perm_schur_primes(int n, int extra, uint32_t *primes, int max_primes, int *k);
+/* The same primes under the name the interface plan gives the helper. */
+int perm_pick_primes(int n, int extra, uint32_t *primes, int max_primes, int *k);
 
 /* The Schur residue matrix (g^(jk) mod p), j,k = 0..n-1, with g the primitive
  * n-th root of unity h^((p-1)/n) for the smallest h >= 2 of exact order n

@@ -307,13 +307,36 @@ int plan(perm_ctx *ctx, const std::vector<MatIn> &in, Plan &pl)
     int chunk[V_COUNT][NMAX + 1];
     for (auto &row : chunk)
         for (int &c : row) c = -1;
-    // items per group, each group sorted largest first (stable)
+    // items per group, each group sorted largest first (stable): key =
+    // indices per item x cost of a step, so that the waves of a block, which
+    // take neighbouring items, finish together in a fused launch of mixed
+    // orders.  A whole range splits into items that are all alike, so when
+    // every matrix of the group is whole the matrices are ordered instead of
+    // the items (the same order, at a fraction of the cost); a matrix's
+    // partial slots stay contiguous and in index order either way.
     for (size_t g = 0; g < groups.size(); ++g) {
         Group gd = gdesc[g];
         gd.first_item = (uint32_t)pl.items.size();
         std::vector<WaveItem> &gi = pl.items;            // the group's items are appended
         const size_t g0 = gi.size();
-        for (uint32_t m : groups[g]) {
+        std::vector<uint32_t> &mats = groups[g];
+        bool all_full = true;
+        for (uint32_t m : mats) all_full = all_full && in[m].full;
+        if (all_full && mats.size() > 1) {
+            std::vector<std::pair<uint64_t, uint32_t>> key(mats.size());
+            for (size_t q = 0; q < mats.size(); ++q) {
+                const MatIn &a = in[mats[q]];
+                int &c = chunk[a.variant][a.n];
+                if (c < 0) c = log2_chunk_for(ctx, a.variant, a.n);
+                const uint64_t T = 1ull << (a.n - 1);
+                key[q] = {std::min<uint64_t>(T, 64ull << c) * step_cost(a.variant, a.n), mats[q]};
+            }
+            std::stable_sort(key.begin(), key.end(),
+                             [](const std::pair<uint64_t, uint32_t> &a,
+                                const std::pair<uint64_t, uint32_t> &b) { return a.first > b.first; });
+            for (size_t q = 0; q < mats.size(); ++q) mats[q] = key[q].second;
+        }
+        for (uint32_t m : mats) {
             const MatIn &a = in[m];
             MatDesc &d = pl.mats[m];
             int &c = chunk[a.variant][a.n];
@@ -327,15 +350,13 @@ int plan(perm_ctx *ctx, const std::vector<MatIn> &in, Plan &pl)
             d.num_parts = np;
             pl.nparts += np;
         }
-        // longest first (stable): key = indices per item x cost of a step, so
-        // that the waves of a block, which take neighbouring items, finish
-        // together in a fused launch of mixed fields
         const size_t cnt = gi.size() - g0;
         auto work = [&](const WaveItem &w) {
             return ((uint64_t)w.nlanes << w.log2L) * step_cost(in[w.mat].variant, in[w.mat].n);
         };
         bool uniform = true;
-        for (size_t q = 1; q < cnt && uniform; ++q) uniform = work(gi[g0 + q]) == work(gi[g0]);
+        if (!all_full)
+            for (size_t q = 1; q < cnt && uniform; ++q) uniform = work(gi[g0 + q]) == work(gi[g0]);
         if (!uniform) {
             std::vector<std::pair<uint64_t, uint32_t>> key(cnt);
             for (size_t q = 0; q < cnt; ++q) key[q] = {work(gi[g0 + q]), (uint32_t)q};
@@ -1075,6 +1096,11 @@ extern "C" int perm_schur_primes(int n, int extra, uint32_t *primes, int max_pri
         }
     }
     return fail(PERM_ERANGE, "bound not reached with 64 primes");
+}
+
+extern "C" int perm_pick_primes(int n, int extra, uint32_t *primes, int max_primes, int *k)
+{
+    return perm_schur_primes(n, extra, primes, max_primes, k);
 }
 
 extern "C" int perm_schur_residues(int n, uint32_t p, uint32_t *out)

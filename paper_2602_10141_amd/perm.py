@@ -74,6 +74,7 @@ _SIGS = {
     "perm_prof_read": ([_P, _P, _P], _I),
     "perm_schur_primes": ([_I, _I, _P, _I, _P], _I),
     "perm_schur_residues": ([_I, ctypes.c_uint32, _P], _I),
+    "perm_pick_primes": ([_I, _I, _P, _I, _P], _I),
     "perm_crt_lift": ([_P, _P, _I, _D, _P, _I, _P, _P], _I),
     "perm_crt_check": ([_P, _P, _I, _D, _P, _I, _P, _P, _P], _I),
     "perm_tune_get": ([_P, _I, _I, _P], _I),
@@ -298,6 +299,13 @@ def perm_schur_primes(n: int, extra: int = 0):
     buf = np.zeros(128, dtype=np.uint32)
     k = ctypes.c_int()
     _check(lib().perm_schur_primes(n, extra, buf.ctypes.data, len(buf), ctypes.byref(k)))
+    return [int(p) for p in buf[:k.value]]
+
+
+def perm_pick_primes(n: int, extra: int = 0):
+    buf = np.zeros(128, dtype=np.uint32)
+    k = ctypes.c_int()
+    _check(lib().perm_pick_primes(n, extra, buf.ctypes.data, len(buf), ctypes.byref(k)))
     return [int(p) for p in buf[:k.value]]
 
 

@@ -51,6 +51,12 @@ def test_schur_primes_match_oracle(P, oracle_lib):
         assert P.perm_schur_primes(n, extra=2) == oracle_lib.crt.primes_for_schur(n, extra=2)
 
 
+def test_pick_primes_is_schur_primes(P):
+    for n in (5, 28, 36):
+        assert P.perm_pick_primes(n) == P.perm_schur_primes(n)
+        assert P.perm_pick_primes(n, extra=3) == P.perm_schur_primes(n, extra=3)
+
+
 def test_schur_residues_match_oracle(P, oracle_lib):
     for n in (3, 7, 12, 28, 36):
         for p in oracle_lib.crt.primes_1_mod_n(n, 2):
