@@ -850,15 +850,16 @@ def bench_stats(P, ctx, args):
 def bench_sizes(P, ctx, args):
     """One matrix per call across the orders of the headline metric: Haar
     U(n) (c128) and O(n) (f64) for n = 20..36 and the Schur matrix S_n mod
-    one prime (F_p) for n = 28..36.  Per case: the call's time and terms/s
-    and the walk kernel's fraction of the FP64 VALU peak.  The chunk length
-    is the library default, i.e. the partition batches use, so a single
-    matrix of order 24..28 occupies only part of the device."""
+    one prime (F_p) for n = 22..36.  Per case: the call's time and terms/s
+    and the walk kernel's fraction of the FP64 VALU peak.  Single calls of
+    orders 16..27 use the latency partition (shorter wave items, so that one
+    matrix occupies the device); from order 28 the batch partition already
+    does."""
     import torch
     from paper_2602_10141_amd import ensembles as E
-    cases = ([("c128", n) for n in (20, 24, 28, 30, 32, 34, 36)] +
-             [("f64", n) for n in (20, 24, 28, 32, 36)] +
-             [("modp", n) for n in (28, 30, 32, 34, 36)])
+    cases = ([("c128", n) for n in (20, 22, 24, 26, 28, 30, 32, 34, 36)] +
+             [("f64", n) for n in (20, 22, 24, 26, 28, 32, 36)] +
+             [("modp", n) for n in (22, 24, 26, 28, 30, 32, 34, 36)])
     rows, tot_terms, tot_s = [], 0, 0.0
     for field, n in cases:
         if field == "c128":

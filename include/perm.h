@@ -35,9 +35,21 @@
  * - A context serialises its calls: a call on a different stream than the
  *   previous one first waits (on the device) for the previous call's work.
  *   A context may be used by one host thread at a time.
+ * - Work partition.  A permanent's Gray range is split into wave items of
+ *   64 lanes x 2^c indices.  Batches (perm_batch, the server) use the
+ *   partition of (field, n) in the tuning table, or the library default,
+ *   whatever else the batch holds, so a float result has the same bits in
+ *   every batch and in the server.  A call whose items at that length would
+ *   leave resident waves idle (one matrix of order up to about 27, a few F_p
+ *   residue matrices) instead uses the latency partition: the chunk length
+ *   that minimises the call's time, down to 2^4 (a table entry for (field,
+ *   n) turns it off).  F_p results are exact under any partition.  A single
+ *   float call (perm_c128, perm_f64) therefore agrees with the same matrix
+ *   in a batch to within rounding (1e-10 of prod_i ||row_i||_2 is the tested
+ *   bound), and bit for bit when called with PERM_SHARED_PARTITION, which
+ *   makes it use the batch partition.
  * - Floating-point results are bit-identical for the same matrix, device and
- *   work partition (the partition depends only on (field, n) and the tuning
- *   table), whether the matrix is computed alone or inside a batch.
+ *   work partition.
  */
 #ifndef PERM_H
 #define PERM_H
@@ -70,6 +82,7 @@ extern "C" {
 #define PERM_DEVICE_PTRS 0x1u  /* matrix/output pointers are device pointers */
 #define PERM_NO_KAHAN    0x2u  /* plain instead of Kahan-compensated float sums */
 #define PERM_MONTGOMERY  0x4u  /* F_p: 32-bit Montgomery walk instead of the FP64 Barrett walk */
+#define PERM_SHARED_PARTITION 0x8u  /* single float calls: the batch partition (see below) */
 
 typedef struct perm_ctx perm_ctx;
 
@@ -98,7 +111,8 @@ int perm_c128(perm_ctx *ctx, const double *A, int n, double *out, unsigned flags
  * and kernels as perm_c128, so the same bits.
  * A: device, n*n complex128 row-major, 8-byte aligned.  out: device, 2
  * doubles (re, im), 8-byte aligned.  flags must contain PERM_DEVICE_PTRS
- * (PERM_NO_KAHAN allowed); asynchronous on `stream` (NULL: the context's).
+ * (PERM_NO_KAHAN, PERM_SHARED_PARTITION allowed); asynchronous on `stream`
+ * (NULL: the context's).
  * 0 <= n <= 32.  Every call on a device shares that device's scratch: calls
  * that overlap on one device (different streams, contexts or threads) race;
  * calls on one stream are ordered.

@@ -31,6 +31,7 @@ struct MatIn {
     uint64_t x0 = 0, x1 = 0;   // else this range
     bool no_scale = false;     // leave the Glynn sum unscaled
     int out_bytes = 16;        // bytes of the result slot written (16, 8 or 4)
+    bool latency = false;      // may use the latency partition (see plan())
 };
 
 // One walk launch.
@@ -95,6 +96,7 @@ struct perm_ctx {
     // reuses it, and its upload when plan_buf still holds it.
     std::vector<permi::MatIn> plan_in;
     std::vector<std::pair<std::pair<int, int>, int>> plan_chunks;
+    std::vector<std::pair<std::pair<int, int>, int>> plan_latency;
     bool plan_cached = false;
     // device address of the static scratch of perm_c128_noalloc on this device
     void *noalloc_ptr = nullptr;
@@ -106,6 +108,7 @@ namespace permi {
 int ensure(perm_ctx *ctx, DevBuf &b, size_t bytes);
 int default_log2_chunk(int variant, int n);
 int log2_chunk_for(const perm_ctx *ctx, int variant, int n);
+int latency_log2_chunk(const perm_ctx *ctx, int variant, int n, uint64_t nmats, int blocks_per_cu);
 int plan(perm_ctx *ctx, const std::vector<MatIn> &in, Plan &pl);
 int begin_call(perm_ctx *ctx, hipStream_t s);
 int end_call(perm_ctx *ctx, hipStream_t s);

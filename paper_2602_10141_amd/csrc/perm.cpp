@@ -196,7 +196,62 @@ static bool same_input(const MatIn &a, const MatIn &b)
 {
     return a.variant == b.variant && a.n == b.n && a.p == b.p && a.src_off == b.src_off &&
            a.out_slot == b.out_slot && a.kahan == b.kahan && a.full == b.full && a.x0 == b.x0 &&
-           a.x1 == b.x1 && a.no_scale == b.no_scale && a.out_bytes == b.out_bytes;
+           a.x1 == b.x1 && a.no_scale == b.no_scale && a.out_bytes == b.out_bytes &&
+           a.latency == b.latency;
+}
+
+static int occupancy(perm_ctx *ctx, const Group &g);
+
+static int occupancy_of(perm_ctx *ctx, int variant, int n, bool kahan)
+{
+    Group g{};
+    g.variant = variant;
+    g.n = n;
+    g.kahan = kahan;
+    g.fused = false;
+    return occupancy(ctx, g);
+}
+
+// The latency partition.  The default chunk length of (variant, n) is set
+// for batches that fill the device; a call with only `nmats` whole matrices
+// of that kind may leave most resident waves idle (one c128 matrix of order
+// 24 is 128 items on 3,072 resident waves).  Its time is about
+//   ceil(items / slots) x (2^c x step cost + seed cost + item cost)
+// per lane; the chunk length minimising it (down to 2^4) is used, the
+// default when that fills the device already.  Below order 16 a whole call
+// is a few microseconds of walk in one block, which the two extra launches
+// of a multi-block call would outweigh, so the default stays.  Only F_p
+// results (exact) and single float calls without PERM_SHARED_PARTITION take
+// it: the summation order of a float result follows the partition.
+int latency_log2_chunk(const perm_ctx *ctx, int variant, int n, uint64_t nmats, int blocks_per_cu)
+{
+    const int c0 = log2_chunk_for(ctx, variant, n);
+    if (n < 16) return c0;
+    const int field = variant == V_MONT ? PERM_MODP : variant;
+    auto it = ctx->tune.find({field, n});
+    if (it != ctx->tune.end() && it->second.log2_chunk > 0) return c0;   // the table decides
+    // two waves per SIMD already issue close to every cycle (four independent
+    // product chains per lane), so a round is two waves per SIMD at most
+    const uint64_t slots =
+        (uint64_t)std::min(std::max(blocks_per_cu, 1), 2) * ctx->num_cus * (BLOCK / WAVE);
+    const uint64_t T = 1ull << (n - 1);
+    auto items = [&](int c) { return nmats * (T >= (64ull << c) ? T >> (6 + c) : 1ull); };
+    if (items(c0) >= slots) return c0;
+    // seed: n - 1 column updates of the n row sums (two words each for
+    // c128); per item about 64 more (claim, descriptor loads, wave sum)
+    const double seed = (double)(n - 1) * n * (variant == V_C128 ? 2.0 : 1.0) + 64.0;
+    const double step = (double)step_cost(variant, n);
+    int best = c0;
+    double best_t = 1e300;
+    for (int c = c0; c >= 4; --c) {
+        const double rounds = std::ceil((double)items(c) / (double)slots);
+        const double t = rounds * (std::ldexp(1.0, c) * step + seed);
+        if (t < 0.98 * best_t) {          // a shorter chunk only when clearly faster
+            best_t = t;
+            best = c;
+        }
+    }
+    return best;
 }
 
 // Plans of at most this many matrices are cached (repeated small calls such
@@ -212,6 +267,15 @@ int plan(perm_ctx *ctx, const std::vector<MatIn> &in, Plan &pl)
         for (size_t q = 0; q < ctx->plan_chunks.size() && hit; ++q) {
             const auto &e = ctx->plan_chunks[q];
             hit = log2_chunk_for(ctx, e.first.first, e.first.second) == e.second;
+        }
+        for (size_t q = 0; q < ctx->plan_latency.size() && hit; ++q) {
+            const auto &e = ctx->plan_latency[q];
+            uint64_t cnt = 0;
+            for (const MatIn &a : in)
+                cnt += a.latency && a.full && a.variant == e.first.first && a.n == e.first.second;
+            hit = latency_log2_chunk(ctx, e.first.first, e.first.second, cnt,
+                                     occupancy_of(ctx, e.first.first, e.first.second, in[0].kahan)) ==
+                  e.second;
         }
         if (hit) return PERM_OK;                 // pl still holds that plan
     }
@@ -303,10 +367,31 @@ int plan(perm_ctx *ctx, const std::vector<MatIn> &in, Plan &pl)
         d.out_slot = a.out_slot;
         if (a.n > 0) pl.stage_bytes += (stage_bytes(a.variant, a.n) + 255) & ~(size_t)255;
     }
-    // chunk length per (variant, n), looked up once per call
+    // chunk length per (variant, n), looked up once per call; matrices that
+    // may take the latency partition get theirs from the count of whole
+    // matrices of their kind in the call
     int chunk[V_COUNT][NMAX + 1];
     for (auto &row : chunk)
         for (int &c : row) c = -1;
+    int lchunk[V_COUNT][NMAX + 1];
+    {
+        uint64_t cnt[V_COUNT][NMAX + 1] = {};
+        bool any = false;
+        for (const MatIn &a : in)
+            if (a.latency && a.full && a.n > 0) { cnt[a.variant][a.n]++; any = true; }
+        for (int v = 0; v < V_COUNT; ++v)
+            for (int n = 0; n <= NMAX; ++n)
+                lchunk[v][n] = (any && cnt[v][n])
+                                   ? latency_log2_chunk(ctx, v, n, cnt[v][n],
+                                                        occupancy_of(ctx, v, n, in[0].kahan))
+                                   : -1;
+    }
+    auto chunk_of = [&](const MatIn &a) {
+        if (a.latency && a.full && lchunk[a.variant][a.n] >= 0) return lchunk[a.variant][a.n];
+        int &c = chunk[a.variant][a.n];
+        if (c < 0) c = log2_chunk_for(ctx, a.variant, a.n);
+        return c;
+    };
     // items per group, each group sorted largest first (stable): key =
     // indices per item x cost of a step, so that the waves of a block, which
     // take neighbouring items, finish together in a fused launch of mixed
@@ -326,21 +411,23 @@ int plan(perm_ctx *ctx, const std::vector<MatIn> &in, Plan &pl)
             std::vector<std::pair<uint64_t, uint32_t>> key(mats.size());
             for (size_t q = 0; q < mats.size(); ++q) {
                 const MatIn &a = in[mats[q]];
-                int &c = chunk[a.variant][a.n];
-                if (c < 0) c = log2_chunk_for(ctx, a.variant, a.n);
+                const int c = chunk_of(a);
                 const uint64_t T = 1ull << (a.n - 1);
                 key[q] = {std::min<uint64_t>(T, 64ull << c) * step_cost(a.variant, a.n), mats[q]};
             }
-            std::stable_sort(key.begin(), key.end(),
-                             [](const std::pair<uint64_t, uint32_t> &a,
-                                const std::pair<uint64_t, uint32_t> &b) { return a.first > b.first; });
-            for (size_t q = 0; q < mats.size(); ++q) mats[q] = key[q].second;
+            bool sorted = true;
+            for (size_t q = 1; q < key.size() && sorted; ++q) sorted = key[q].first <= key[q - 1].first;
+            if (!sorted) {
+                std::stable_sort(key.begin(), key.end(),
+                                 [](const std::pair<uint64_t, uint32_t> &a,
+                                    const std::pair<uint64_t, uint32_t> &b) { return a.first > b.first; });
+                for (size_t q = 0; q < mats.size(); ++q) mats[q] = key[q].second;
+            }
         }
         for (uint32_t m : mats) {
             const MatIn &a = in[m];
             MatDesc &d = pl.mats[m];
-            int &c = chunk[a.variant][a.n];
-            if (c < 0) c = log2_chunk_for(ctx, a.variant, a.n);
+            const int c = chunk_of(a);
             const uint64_t T = 1ull << (a.n - 1);
             const uint64_t x0 = a.full ? 0 : a.x0;
             const uint64_t x1 = a.full ? T : a.x1;
@@ -376,6 +463,10 @@ int plan(perm_ctx *ctx, const std::vector<MatIn> &in, Plan &pl)
         for (int v = 0; v < V_COUNT; ++v)
             for (int n = 0; n <= NMAX; ++n)
                 if (chunk[v][n] >= 0) ctx->plan_chunks.push_back({{v, n}, chunk[v][n]});
+        ctx->plan_latency.clear();
+        for (int v = 0; v < V_COUNT; ++v)
+            for (int n = 0; n <= NMAX; ++n)
+                if (lchunk[v][n] >= 0) ctx->plan_latency.push_back({{v, n}, lchunk[v][n]});
         ctx->plan_cached = true;
     }
     return PERM_OK;
@@ -657,6 +748,7 @@ static int single(perm_ctx *ctx, int variant, const void *A, int n, uint32_t p, 
     in[0].p = p;
     in[0].kahan = !(flags & PERM_NO_KAHAN);
     in[0].full = true;
+    in[0].latency = variant == V_MODP || variant == V_MONT || !(flags & PERM_SHARED_PARTITION);
     // A device output with the alignment of its element type receives the
     // result straight from the finalize step (only out_bytes written), with
     // no copy launch; otherwise the 16-byte slot goes through ctx->outs.
@@ -712,7 +804,7 @@ extern "C" int perm_c128_noalloc(perm_ctx *ctx, const double *A, int n, double *
     if (!ctx) return fail(PERM_EINVAL, "ctx is NULL");
     if (!(flags & PERM_DEVICE_PTRS))
         return fail(PERM_EINVAL, "perm_c128_noalloc takes device pointers only (PERM_DEVICE_PTRS)");
-    if (flags & ~(PERM_DEVICE_PTRS | PERM_NO_KAHAN))
+    if (flags & ~(PERM_DEVICE_PTRS | PERM_NO_KAHAN | PERM_SHARED_PARTITION))
         return fail(PERM_EINVAL, "perm_c128_noalloc: unsupported flags 0x%x", flags);
     if (n < 0 || n > NOALLOC_NMAX)
         return fail(PERM_EINVAL, "n = %d outside [0, %d], the orders of the no-allocation call", n,
@@ -726,8 +818,19 @@ extern "C" int perm_c128_noalloc(perm_ctx *ctx, const double *A, int n, double *
     // 2^c indices, or one item of fewer indices for a short range
     uint64_t count = 0;
     uint32_t log2L = 0, nlanes = 0;
+    // occupancy from the context's cache when it has it (no insertion: the
+    // call allocates nothing, host memory included)
+    int occ = 0;
     if (n > 0) {
-        const int c = log2_chunk_for(ctx, V_C128, n);
+        const int key = V_C128 * 200 + n * 2 + (kahan ? 1 : 0);
+        auto it = ctx->occ.find(key);
+        if (it != ctx->occ.end()) occ = it->second;
+        else if (walk_occupancy(V_C128, n, kahan, false, 0, &occ) != 0 || occ < 1) occ = 1;
+    }
+    if (n > 0) {
+        // the chunk length perm_c128 uses for the same flags
+        const int c = (flags & PERM_SHARED_PARTITION) ? log2_chunk_for(ctx, V_C128, n)
+                                                      : latency_log2_chunk(ctx, V_C128, n, 1, occ);
         const uint64_t T = 1ull << (n - 1);
         const uint64_t W = 64ull << c;
         if (T >= W) {
@@ -756,11 +859,6 @@ extern "C" int perm_c128_noalloc(perm_ctx *ctx, const double *A, int n, double *
                                            kahan ? MD_KAHAN : 0u, out, s));
     if (n > 0) {
         // launch shape as execute() picks it for this one group
-        int occ = 0;
-        const int key = V_C128 * 200 + n * 2 + (kahan ? 1 : 0);
-        auto it = ctx->occ.find(key);
-        if (it != ctx->occ.end()) occ = it->second;
-        else if (walk_occupancy(V_C128, n, kahan, false, 0, &occ) != 0 || occ < 1) occ = 1;
         const int per_cu = ctx->grid_per_cu > 0 ? std::min(ctx->grid_per_cu, occ) : occ;
         const uint32_t cnt = (uint32_t)count;
         const uint32_t resident = (uint32_t)(per_cu * ctx->num_cus * (BLOCK / WAVE));
@@ -835,6 +933,7 @@ extern "C" int perm_batch(perm_ctx *ctx, const perm_item *items, int count, cons
         in[i].out_slot = (uint32_t)i;
         in[i].kahan = !(flags & PERM_NO_KAHAN);
         in[i].full = true;
+        in[i].latency = items[i].field == PERM_MODP;   // exact whatever the partition
     }
     Plan &pl = ctx->scratch_plan;
     if ((rc = plan(ctx, in, pl)) != PERM_OK) return rc;
@@ -1017,6 +1116,7 @@ extern "C" int perm_crt_int(perm_ctx *ctx, const uint32_t *mats, const uint32_t 
         in[i].src_off = per * i;
         in[i].out_slot = (uint32_t)i;
         in[i].full = true;
+        in[i].latency = true;              // exact: any partition gives the same residues
     }
     Plan &pl = ctx->scratch_plan;
     if ((rc = plan(ctx, in, pl)) != PERM_OK) return rc;

@@ -21,7 +21,7 @@ LIB_PATH = os.path.join(_HERE, "libperm.so")
 PERM_OK, PERM_EINVAL, PERM_ERANGE, PERM_ENOMEM, PERM_EDEVICE, PERM_EAGAIN, PERM_ENOTFOUND, \
     PERM_ECANCELED = range(8)
 PERM_C128, PERM_F64, PERM_MODP = 0, 1, 2
-PERM_DEVICE_PTRS, PERM_NO_KAHAN, PERM_MONTGOMERY = 0x1, 0x2, 0x4
+PERM_DEVICE_PTRS, PERM_NO_KAHAN, PERM_MONTGOMERY, PERM_SHARED_PARTITION = 0x1, 0x2, 0x4, 0x8
 PERM_NMAX = 48
 FIELDS = {"c128": PERM_C128, "f64": PERM_F64, "modp": PERM_MODP}
 

@@ -269,20 +269,58 @@ def test_batch_mixed_matches_single_bitwise(P, ctx, O):
     vals = P.batch_values(items, out)
     for (A, field, p), v in zip(mats, vals):
         n = A.shape[0]
+        # a single call with the batch partition has the batch's bits; the
+        # default single call (the latency partition from order 16) agrees
+        # to within the tolerance
         if field == "c128":
-            single = P.perm_c128(ctx, A)
-            assert v == single
+            assert v == P.perm_c128(ctx, A, flags=P.PERM_SHARED_PARTITION)
+            assert abs(v - P.perm_c128(ctx, A)) <= TOL * scale(A)
             if n <= 16:
                 assert abs(v - (O.native.ryser_c128(A) if n else 1)) <= TOL * scale(A)
         elif field == "f64":
-            single = P.perm_f64(ctx, A)
-            assert v == single
+            assert v == P.perm_f64(ctx, A, flags=P.PERM_SHARED_PARTITION)
+            assert abs(v - P.perm_f64(ctx, A)) <= TOL * scale(A)
             if n <= 16:
                 assert abs(v - (O.native.ryser_f64(A) if n else 1)) <= TOL * scale(A)
         else:
             assert v == P.perm_modp(ctx, A, p)
             if n <= 16:
                 assert v == (O.native.ryser_modp(A, p) if n else 1)
+
+
+@pytest.mark.parametrize("field,n", [("c128", 16), ("c128", 20), ("c128", 22), ("c128", 24),
+                                     ("c128", 26), ("f64", 20), ("f64", 24), ("f64", 27),
+                                     ("modp", 20), ("modp", 24)])
+def test_latency_partition_single_calls(P, ctx, O, field, n):
+    """One matrix of order 16..27 alone would leave most resident waves idle
+    at the batch partition, so a single call splits it into more, shorter
+    wave items.  The result agrees with the oracle (orders up to 24) and
+    with the same matrix in a batch to within the tolerance (bit for bit for
+    F_p), and with PERM_SHARED_PARTITION it has the batch's bits."""
+    import concurrent.futures as cf
+    g = E.rng(15, n)
+    p = 1073742209
+    if field == "c128":
+        A = E.haar_unitary(n, g)
+    elif field == "f64":
+        A = E.haar_orthogonal(n, g)
+    else:
+        A = E.random_residues(n, p, g)
+    items, data = P.pack_matrices([(A, field, p if field == "modp" else 0)])
+    batch = P.batch_values(items, P.perm_batch(ctx, items, data))[0]
+    if field == "modp":
+        assert P.perm_modp(ctx, A, p) == batch == O.native.ryser_modp_threaded(A, p)
+        assert P.perm_modp(ctx, A, p, flags=P.PERM_MONTGOMERY) == batch
+        return
+    fn = P.perm_c128 if field == "c128" else P.perm_f64
+    single = fn(ctx, A)
+    assert abs(single - batch) <= TOL * scale(A)
+    assert fn(ctx, A, flags=P.PERM_SHARED_PARTITION) == batch
+    if n <= 24:
+        with cf.ThreadPoolExecutor(1) as ex:
+            want = ex.submit(O.native.ryser_c128 if field == "c128" else O.native.ryser_f64, A).result()
+        assert abs(single - want) <= TOL * scale(A)
+        assert abs(batch - want) <= TOL * scale(A)
 
 
 def test_batch_device_path_and_bad_item(P, ctx):
