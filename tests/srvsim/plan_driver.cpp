@@ -155,6 +155,56 @@ static void check_tune_files(perm_ctx *ctx)
     unlink(path);
 }
 
+// The latency partition: a lone matrix whose batch partition leaves
+// resident waves idle is split finer (never below 2^4 indices per lane, and
+// never for orders below 16); the batch partition stays for calls that fill
+// the device, for matrices not marked latency-eligible, and for (field, n)
+// with a tuning-table entry.  Either way the range is tiled exactly once.
+static void check_latency_partition(perm_ctx *ctx)
+{
+    ctx->tune.clear();
+    ctx->num_cus = 256;
+    const uint64_t slots = 2ull * 256 * 4;     // the stub occupancy is 3 blocks per CU
+    Plan pl;
+    for (int variant : {(int)V_C128, (int)V_F64, (int)V_MODP})
+        for (int n = 12; n <= 32; ++n) {
+            std::vector<MatIn> in(1);
+            in[0].variant = variant;
+            in[0].n = n;
+            in[0].p = variant == V_MODP ? 2147483647u : 0;
+            in[0].latency = true;
+            plan(ctx, in, pl);
+            check_plan(ctx, in, pl);
+            const uint32_t lat_items = (uint32_t)pl.items.size();
+            const uint32_t lat_c = pl.items[0].log2L;
+            in[0].latency = false;
+            plan(ctx, in, pl);
+            check_plan(ctx, in, pl);
+            const uint32_t items = (uint32_t)pl.items.size();
+            const uint32_t c0 = pl.items[0].log2L;
+            if (n < 16 || items >= slots) {
+                CHECK(lat_items == items, "v%d n=%d: latency partition where the batch one fills", variant, n);
+            } else {
+                CHECK(lat_c <= c0 && (lat_c >= 4 || lat_c == c0), "v%d n=%d: chunk 2^%u", variant, n, lat_c);
+                CHECK(lat_items >= items, "v%d n=%d: fewer items", variant, n);
+            }
+            // a table entry decides
+            perm_tune t{c0 > 4 ? (int)c0 - 1 : (int)c0, 0};
+            perm_tune_set(ctx, variant == V_MODP ? PERM_MODP : variant, n, &t);
+            in[0].latency = true;
+            plan(ctx, in, pl);
+            CHECK(pl.items[0].log2L == (uint32_t)t.log2_chunk, "v%d n=%d: table entry ignored", variant, n);
+            ctx->tune.clear();
+        }
+    // one c128 matrix of order 24 fills two waves per SIMD
+    std::vector<MatIn> in(1);
+    in[0].variant = V_C128;
+    in[0].n = 24;
+    in[0].latency = true;
+    plan(ctx, in, pl);
+    CHECK(pl.items.size() >= slots, "U(24) alone: %zu items", pl.items.size());
+}
+
 int main()
 {
     perm_ctx *ctx = nullptr;
@@ -208,6 +258,7 @@ int main()
     plan(ctx, in, pl);
     CHECK(ctx->plan_id != id, "changed input reused the plan");
     check_tune_files(ctx);
+    check_latency_partition(ctx);
     perm_ctx_destroy(ctx);
     printf("planner checks: %d failures\n", failures);
     fflush(stdout);
