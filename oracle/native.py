@@ -31,6 +31,8 @@ def lib():
             ("oracle_ryser_modp", [u32p, c_int, c_u32, u32p]),
             ("oracle_ryser_modp_prefix", [u32p, c_int, c_u32, u64, u32p]),
             ("oracle_ryser_modp_range", [u32p, c_int, c_u32, u64, u64, u32p]),
+            ("oracle_ryser_c128_range", [dp, c_int, u64, u64, dp]),
+            ("oracle_ryser_f64_range", [dp, c_int, u64, u64, dp]),
             ("oracle_glynn_range_c128", [dp, c_int, u64, u64, dp]),
             ("oracle_glynn_range_f64", [dp, c_int, u64, u64, dp]),
             ("oracle_glynn_range_modp", [u32p, c_int, c_u32, u64, u64, u32p]),
@@ -127,6 +129,40 @@ def ryser_modp_threaded(A, p: int, threads: int = None) -> int:
         parts = list(ex.map(lambda s: ryser_modp_range(A, p, *s), _spans(1, 1 << n, 4 * threads)))
     tot = sum(parts) % p
     return (p - tot) % p if n % 2 else tot
+
+
+def ryser_float_range(A, x0: int, x1: int):
+    """Signed Ryser sum (complex128 or float64 walk, Kahan-summed) over the
+    Gray-ordered subsets x in [x0, x1), 1 <= x0 <= x1 <= 2^n, without the
+    final (-1)^n."""
+    if np.iscomplexobj(A):
+        A, n = _mat(A, np.complex128)
+        out = np.zeros(2)
+        _check(lib().oracle_ryser_c128_range(A.ctypes.data, n, x0, x1, out.ctypes.data))
+        return complex(out[0], out[1])
+    A, n = _mat(A, np.float64)
+    out = np.zeros(1)
+    _check(lib().oracle_ryser_f64_range(A.ctypes.data, n, x0, x1, out.ctypes.data))
+    return float(out[0])
+
+
+def ryser_float_threaded(A, threads: int = None):
+    """perm(A) for a complex128 or float64 matrix by Ryser's formula, the
+    subset range [1, 2^n) split into contiguous pieces on host threads; the
+    pieces' sums are added with math.fsum per component."""
+    import math
+    cplx = np.iscomplexobj(A)
+    A = np.ascontiguousarray(A, dtype=np.complex128 if cplx else np.float64)
+    n = A.shape[0]
+    if n == 0:
+        return 1.0
+    threads = threads or default_threads()
+    with cf.ThreadPoolExecutor(threads) as ex:
+        parts = list(ex.map(lambda s: ryser_float_range(A, *s), _spans(1, 1 << n, 4 * threads)))
+    sign = -1.0 if n % 2 else 1.0
+    if cplx:
+        return sign * complex(math.fsum(z.real for z in parts), math.fsum(z.imag for z in parts))
+    return sign * math.fsum(parts)
 
 
 def glynn_range_threaded(A, x0: int, x1: int, field: str, p: int = 0, threads: int = None):

@@ -148,6 +148,79 @@ int oracle_ryser_f64(const double *A, int n, int kahan, double *out)
     return 0;
 }
 
+/* --------------------------------------------- float sums over subset ranges */
+/* The signed Ryser sums of the two walks above over the Gray-ordered subsets
+ * x in [x_begin, x_end) (1 <= x_begin <= x_end <= 2^n), without the final
+ * (-1)^n, Kahan-summed per component.  The row sums start as those of the
+ * subset gray(x_begin - 1), added up column by column; from there each
+ * visit is the whole walk's.  Disjoint ranges covering [1, 2^n) add up to
+ * the whole sum (up to the rounding of that addition), so one permanent can
+ * be spread over host threads. */
+int oracle_ryser_c128_range(const double *A, int n, uint64_t x_begin, uint64_t x_end, double *out)
+{
+    if (n < 1 || n > ORACLE_NMAX || !A || !out) return -1;
+    if (x_begin < 1 || x_begin > x_end || (n < 64 && x_end > ((uint64_t)1 << n))) return -1;
+    double sr[ORACLE_NMAX], si[ORACLE_NMAX];
+    for (int i = 0; i < n; ++i) { sr[i] = 0.0; si[i] = 0.0; }
+    const uint64_t g0 = (x_begin - 1) ^ ((x_begin - 1) >> 1);
+    for (int j = 0; j < n; ++j)
+        if ((g0 >> j) & 1u)
+            for (int i = 0; i < n; ++i) {
+                sr[i] += A[2 * ((size_t)i * n + j)];
+                si[i] += A[2 * ((size_t)i * n + j) + 1];
+            }
+    double tr = 0.0, ti = 0.0, cr = 0.0, ci = 0.0;
+    for (uint64_t x = x_begin; x < x_end; ++x) {
+        unsigned j = ctz64(x);
+        uint64_t g = x ^ (x >> 1);
+        int enters = (int)((g >> j) & 1u);
+        for (int i = 0; i < n; ++i) {
+            double ar = A[2 * ((size_t)i * n + j)], ai = A[2 * ((size_t)i * n + j) + 1];
+            if (enters) { sr[i] += ar; si[i] += ai; }
+            else        { sr[i] -= ar; si[i] -= ai; }
+        }
+        double pr = sr[0], pi = si[0];
+        for (int i = 1; i < n; ++i) {
+            double qr = pr * sr[i] - pi * si[i];
+            double qi = pr * si[i] + pi * sr[i];
+            pr = qr; pi = qi;
+        }
+        if (x & 1u) { pr = -pr; pi = -pi; }
+        double y = pr - cr, t = tr + y; cr = (t - tr) - y; tr = t;
+        y = pi - ci; t = ti + y; ci = (t - ti) - y; ti = t;
+    }
+    out[0] = tr; out[1] = ti;
+    return 0;
+}
+
+int oracle_ryser_f64_range(const double *A, int n, uint64_t x_begin, uint64_t x_end, double *out)
+{
+    if (n < 1 || n > ORACLE_NMAX || !A || !out) return -1;
+    if (x_begin < 1 || x_begin > x_end || (n < 64 && x_end > ((uint64_t)1 << n))) return -1;
+    double s[ORACLE_NMAX];
+    for (int i = 0; i < n; ++i) s[i] = 0.0;
+    const uint64_t g0 = (x_begin - 1) ^ ((x_begin - 1) >> 1);
+    for (int j = 0; j < n; ++j)
+        if ((g0 >> j) & 1u)
+            for (int i = 0; i < n; ++i) s[i] += A[(size_t)i * n + j];
+    double tot = 0.0, c = 0.0;
+    for (uint64_t x = x_begin; x < x_end; ++x) {
+        unsigned j = ctz64(x);
+        uint64_t g = x ^ (x >> 1);
+        int enters = (int)((g >> j) & 1u);
+        for (int i = 0; i < n; ++i) {
+            if (enters) s[i] += A[(size_t)i * n + j];
+            else        s[i] -= A[(size_t)i * n + j];
+        }
+        double p = s[0];
+        for (int i = 1; i < n; ++i) p *= s[i];
+        if (x & 1u) p = -p;
+        double y = p - c, t = tot + y; c = (t - tot) - y; tot = t;
+    }
+    out[0] = tot;
+    return 0;
+}
+
 /* ----------------------------------------------------------------- F_p */
 /* Signed Ryser sum over the Gray-ordered subsets x = x_begin .. x_end-1
  * (x_begin >= 1), mod p, without the final (-1)^n.  The row sums start as

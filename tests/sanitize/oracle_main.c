@@ -15,6 +15,8 @@ int oracle_ryser_modp(const uint32_t *A, int n, uint32_t p, uint32_t *out);
 int oracle_ryser_modp_prefix(const uint32_t *A, int n, uint32_t p, uint64_t x_end, uint32_t *out);
 int oracle_ryser_modp_range(const uint32_t *A, int n, uint32_t p, uint64_t x0, uint64_t x1,
                             uint32_t *out);
+int oracle_ryser_c128_range(const double *A, int n, uint64_t x0, uint64_t x1, double *out);
+int oracle_ryser_f64_range(const double *A, int n, uint64_t x0, uint64_t x1, double *out);
 int oracle_glynn_range_c128(const double *A, int n, uint64_t x0, uint64_t x1, double *out);
 int oracle_glynn_range_f64(const double *A, int n, uint64_t x0, uint64_t x1, double *out);
 int oracle_glynn_range_modp(const uint32_t *A, int n, uint32_t p, uint64_t x0, uint64_t x1,
@@ -66,6 +68,10 @@ int main(void)
             EXPECT(oracle_ryser_modp_range(M, n, 2147483647u, 3 < S ? 3 : S, 3 < S ? 3 : S, o32) == 0);
             EXPECT(oracle_ryser_modp_range(M, n, 2147483647u, 0, 1, o32) == -1);      /* x0 >= 1 */
             EXPECT(oracle_ryser_modp_range(M, n, 2147483647u, 1, S + 1, o32) == -1);  /* past 2^n */
+            EXPECT(oracle_ryser_c128_range(C, n, 1, S, out2) == 0);
+            EXPECT(oracle_ryser_c128_range(C, n, S / 2 + 1, S, out2) == 0);
+            EXPECT(oracle_ryser_f64_range(R, n, 1, S, out2) == 0);
+            EXPECT(oracle_ryser_f64_range(R, n, 0, 1, out2) == -1);
             EXPECT(oracle_glynn_range_c128(C, n, 0, T, out2) == 0);
             EXPECT(oracle_glynn_range_c128(C, n, T, T, out2) == 0);
             EXPECT(oracle_glynn_range_f64(R, n, 0, T, out2) == 0);

@@ -326,6 +326,37 @@ def test_ryser_modp_threaded_equals_laplace(O):
         assert O.native.ryser_modp_threaded(R, p, threads=5) == exact % p
 
 
+@pytest.mark.parametrize("n", [1, 2, 3, 5, 7])
+def test_ryser_float_ranges_add_up_to_bruteforce(O, n):
+    """Complex and real Ryser sums over random partitions of [1, 2^n), each
+    range seeded from its first subset, add up to perm(A) from the
+    definition, up to the sign (-1)^n."""
+    A = _cplx(n, 910 + n)
+    R = A.real.copy()
+    scale = max(1.0, float(np.prod(np.linalg.norm(A, axis=1))))
+    wc = O.reference.bruteforce(A.tolist())
+    wr = O.reference.bruteforce(R.tolist())
+    g = random.Random(100 + n)
+    end = 1 << n
+    sign = -1 if n % 2 else 1
+    for _ in range(6):
+        cuts = sorted({1, end, *(g.randrange(1, end + 1) for _ in range(g.randrange(0, 5)))})
+        zc = sum(O.native.ryser_float_range(A, a, b) for a, b in zip(cuts, cuts[1:]))
+        zr = sum(O.native.ryser_float_range(R, a, b) for a, b in zip(cuts, cuts[1:]))
+        assert abs(sign * zc - wc) <= 1e-13 * scale
+        assert abs(sign * zr - wr) <= 1e-13 * scale
+    assert abs(O.native.ryser_float_threaded(A, threads=3) - wc) <= 1e-13 * scale
+
+
+def test_ryser_float_threaded_matches_the_whole_walk(O):
+    for n in (12, 15):
+        A = _cplx(n, 920 + n)
+        scale = float(np.prod(np.linalg.norm(A, axis=1)))
+        assert abs(O.native.ryser_float_threaded(A, threads=5) - O.native.ryser_c128(A)) <= 1e-12 * scale
+        R = A.real.copy()
+        assert abs(O.native.ryser_float_threaded(R, threads=5) - O.native.ryser_f64(R)) <= 1e-12 * scale
+
+
 def test_glynn_range_threaded_is_the_plain_range(O):
     n, p = 12, 1073742209
     M = E.random_residues(n, p, E.rng(908, 0))
