@@ -13,6 +13,8 @@
   walks run; shorter windows only reach the chunk-end code paths.
 * Geodesic points of orders 19..25 from the serving stream, in the batch
   form and partition the serving benchmark uses, against the oracle.
+* Whole c128 permanents of orders 25..30 and an f64 one of order 28 in every
+  call form, against the oracle's full Ryser sum on host threads.
 
 Floats: |gpu - oracle| <= 1e-10 * prod_i ||row_i||_2 for permanents and
 1e-10 * prod_i ||row_i||_2 * sqrt(x1 - x0) for unscaled window sums (a sum of
@@ -101,6 +103,31 @@ def test_random_residues_n28_full_permanent(P, ctx, random28, mont):
     out = P.perm_modp(ctx, torch.from_numpy(A.astype(np.int32)).cuda(), p, flags=flags)
     torch.cuda.synchronize()
     assert int(out.cpu()[0]) == want                                         # device pointers
+
+
+# ------------------------------------------- whole float permanents, n >= 25
+@pytest.mark.parametrize("field,n", [("c128", 25), ("c128", 26), ("c128", 28), ("c128", 30),
+                                     ("f64", 28)])
+def test_whole_float_permanents_large(P, ctx, oracle_lib, field, n):
+    """Whole permanents of orders 25..30 (the large-order c128 kernels) in
+    all three call forms -- a single call (the latency partition below order
+    28), a single call with the batch partition, a batch of two -- against
+    the oracle's full Ryser sum on host threads."""
+    g = E.rng(64, n)
+    A = E.haar_unitary(n, g) if field == "c128" else E.haar_orthogonal(n, g)
+    B = E.haar_unitary(n, g) if field == "c128" else E.haar_orthogonal(n, g)
+    say(f"{field} n={n}: oracle on host threads")
+    want = oracle_lib.native.ryser_float_threaded(A)
+    fn = P.perm_c128 if field == "c128" else P.perm_f64
+    single = fn(ctx, A)
+    shared = fn(ctx, A, flags=P.PERM_SHARED_PARTITION)
+    items, data = P.pack_matrices([(A, field, 0), (B, field, 0)])
+    batch = P.batch_values(items, P.perm_batch(ctx, items, data))
+    tol = TOL * scale(A)
+    assert abs(single - want) <= tol, (single, want)
+    assert abs(shared - want) <= tol, (shared, want)
+    assert batch[0] == shared
+    assert abs(want) <= 1 + 1e-12                       # |perm| <= 1 for orthogonal/unitary
 
 
 # ---------------------------------------------------- whole default items
