@@ -350,7 +350,8 @@ def test_block_claims_small_grids(P, ctx, O, count):
     items, data = P.pack_matrices(mats)
     vals = P.batch_values(items, P.perm_batch(ctx, items, data))
     for (A, _, _), v in zip(mats, vals):
-        assert v == P.perm_c128(ctx, A)
+        assert v == P.perm_c128(ctx, A, flags=P.PERM_SHARED_PARTITION)
+        assert abs(P.perm_c128(ctx, A) - v) <= TOL * scale(A)
         assert abs(v - O.native.ryser_c128(A)) <= TOL * scale(A)
 
 

@@ -132,7 +132,8 @@ def test_cancel(P, ctx):
             srv.wait(big[0], big[1], timeout_s=60)
         assert e.value.status == P.PERM_ECANCELED
         v = srv.wait(small[0], small[1], timeout_s=60)
-        assert v == P.perm_c128(ctx, E.ginibre_complex(10, E.rng(25, 1)))
+        assert v == P.perm_c128(ctx, E.ginibre_complex(10, E.rng(25, 1)),
+                                flags=P.PERM_SHARED_PARTITION)
         st = srv.stats()
         assert st["canceled"] >= 1
     finally:
