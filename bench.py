@@ -688,8 +688,8 @@ def sub_serve(P, ctx, args, loads=(0.5, 0.7, 0.9)):
     saturation rate; latency from submit to the result on the host, p50/p99
     per class.  The walk launches of the saturation run are timed with HIP
     events on the server's streams; two slices overlap on the device, so the
-    summed launch durations exceed the busy time and the fraction is a lower
-    bound."""
+    summed launch durations exceed the busy time and the per-launch fraction
+    is a lower bound; the whole-job fractions beside it are not."""
     reqs = serve_requests(P)
     serve_tuning(P, ctx)
     try:
@@ -708,7 +708,11 @@ def sub_serve(P, ctx, args, loads=(0.5, 0.7, 0.9)):
         cls = np.array([r[3] for r in reqs])
         rf = roofline(ops / max(launches, 1), walk_ms, launches, None, flops / ops)
         rf["all_launches_timed"] = launches < SERVE_EVENT_PAIRS
-        rf["busy_frac"] = round(ops / max(st["busy_s"], 1e-9) / PEAK_LANE_OPS, 4)
+        # whole-job fractions of the peak: every request's algorithmic ops over
+        # the time the server had work queued or on the device, and over the
+        # wall time from the first submit to the last result
+        rf["frac_over_busy_time"] = round(ops / max(st["busy_s"], 1e-9) / PEAK_LANE_OPS, 4)
+        rf["frac_over_wall_time"] = round(ops / wall / PEAK_LANE_OPS, 4)
         result = {"saturation": {"wall_s": wall, "requests_per_s": sat_rate,
                                  "terms_per_s": terms / wall, **_pcts(lats),
                                  "slices": st["slices"], "busy_s": st["busy_s"],

@@ -22,8 +22,10 @@
  * - Pointers are host pointers unless PERM_DEVICE_PTRS is set in `flags`, in
  *   which case matrices and outputs named "dev-or-host" are device pointers
  *   (e.g. torch tensor data_ptr()) and the call is asynchronous on `stream`
- *   except where noted.  `stream` is a hipStream_t or NULL for the context's
- *   own stream.  A single-matrix call's device output aligned to its element
+ *   except where noted.  `stream` is a hipStream_t; NULL is HIP's null
+ *   (legacy default) stream, the one PyTorch uses as its default stream, so
+ *   such a call is ordered with PyTorch's work there and with every blocking
+ *   stream.  A single-matrix call's device output aligned to its element
  *   type is written by the kernels directly (exactly its bytes), otherwise
  *   through a device copy.
  * - The caller owns every buffer it passes.  The context owns only its

@@ -736,7 +736,7 @@ static int single(perm_ctx *ctx, int variant, const void *A, int n, uint32_t p, 
     if (!ctx) return fail(PERM_EINVAL, "ctx is NULL");
     if (n < 0 || n > PERM_NMAX) return fail(PERM_EINVAL, "n = %d outside [0, %d]", n, PERM_NMAX);
     if (!out || (n > 0 && !A)) return fail(PERM_EINVAL, "NULL matrix or output pointer");
-    hipStream_t s = stream ? (hipStream_t)stream : ctx->stream;
+    hipStream_t s = (hipStream_t)stream;
     int rc = begin_call(ctx, s);
     if (rc != PERM_OK) return rc;
     const void *src = nullptr;
@@ -851,7 +851,7 @@ extern "C" int perm_c128_noalloc(perm_ctx *ctx, const double *A, int n, double *
         return fail(PERM_ENOMEM,
                     "order %d in %llu wave items needs more than the %zu bytes of static scratch",
                     n, (unsigned long long)count, NOALLOC_SCRATCH_BYTES);
-    hipStream_t s = stream ? (hipStream_t)stream : ctx->stream;
+    hipStream_t s = (hipStream_t)stream;
     int rc = begin_call(ctx, s);
     if (rc != PERM_OK) return rc;
     char *base = (char *)ctx->noalloc_ptr;
@@ -918,7 +918,7 @@ extern "C" int perm_batch(perm_ctx *ctx, const perm_item *items, int count, cons
         span = std::max(span, items[i].offset + bytes);
     }
     if (any_data && !data) return fail(PERM_EINVAL, "data is NULL");
-    hipStream_t s = stream ? (hipStream_t)stream : ctx->stream;
+    hipStream_t s = (hipStream_t)stream;
     int rc = begin_call(ctx, s);
     if (rc != PERM_OK) return rc;
     const void *src = nullptr;
@@ -962,7 +962,7 @@ extern "C" int perm_range(perm_ctx *ctx, const perm_item *item, const void *data
     if (x0 > x1 || x1 > T) return fail(PERM_EINVAL, "range [%llu, %llu) outside [0, 2^%d)",
                                        (unsigned long long)x0, (unsigned long long)x1, item->n - 1);
     if (!data) return fail(PERM_EINVAL, "data is NULL");
-    hipStream_t s = stream ? (hipStream_t)stream : ctx->stream;
+    hipStream_t s = (hipStream_t)stream;
     if ((rc = begin_call(ctx, s)) != PERM_OK) return rc;
     const int variant = variant_of(item->field, flags);
     const uint64_t bytes = (uint64_t)item->n * item->n * src_entry_bytes(variant);
@@ -1101,7 +1101,7 @@ extern "C" int perm_crt_int(perm_ctx *ctx, const uint32_t *mats, const uint32_t 
     if (n > 0 && !mats) return fail(PERM_EINVAL, "mats is NULL");
     int rc = check_primes(primes, k, log2_bound);
     if (rc != PERM_OK) return rc;
-    hipStream_t s = stream ? (hipStream_t)stream : ctx->stream;
+    hipStream_t s = (hipStream_t)stream;
     if ((rc = begin_call(ctx, s)) != PERM_OK) return rc;
     const int variant = variant_of(PERM_MODP, flags);
     const size_t per = (size_t)n * n * 4;

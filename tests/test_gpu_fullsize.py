@@ -78,7 +78,8 @@ def test_ragged_batch_10000(P, ctx, oracle_lib):
     idx = []
     for n in range(8, 25):
         cand = np.flatnonzero(ns == n)
-        idx.extend(g.choice(cand, size=min(len(cand), 18 if n > 20 else 40), replace=False))
+        idx.extend(g.choice(cand, size=min(len(cand), 60), replace=False))
+    assert len(idx) >= 1000
 
     def ora(i):
         A, f, _ = mats[i]
