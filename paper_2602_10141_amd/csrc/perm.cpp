@@ -237,9 +237,13 @@ int latency_log2_chunk(const perm_ctx *ctx, int variant, int n, uint64_t nmats, 
     const uint64_t T = 1ull << (n - 1);
     auto items = [&](int c) { return nmats * (T >= (64ull << c) ? T >> (6 + c) : 1ull); };
     if (items(c0) >= slots) return c0;
-    // seed: n - 1 column updates of the n row sums (two words each for
-    // c128); per item about 64 more (claim, descriptor loads, wave sum)
-    const double seed = (double)(n - 1) * n * (variant == V_C128 ? 2.0 : 1.0) + 64.0;
+    // seed: the wave's common part (about n instructions a lane) and the
+    // seven columns whose signs differ across its lanes, each an update of
+    // the n row sums (two words each for c128; the Montgomery walk updates
+    // for all n - 1 columns); per item about 64 more (claim, descriptor
+    // loads, LDS exchange, wave sum)
+    const int upd = variant == V_MONT ? n - 1 : std::min(n - 1, 7);
+    const double seed = (double)upd * n * (variant == V_C128 ? 2.0 : 1.0) + n + 64.0;
     const double step = (double)step_cost(variant, n);
     int best = c0;
     double best_t = 1e300;

@@ -138,6 +138,16 @@ struct Chains {
 // Column entries held in SGPRs between steps (at most 80 of the 102 SGPRs).
 constexpr int PF_MAX = 40;
 
+// Order LDS writes of some lanes before reads of other lanes of the same
+// wave.  A wave's LDS operations complete in program order, so this only
+// keeps the compiler from moving memory operations across it.
+__device__ __forceinline__ void wave_lds_sync()
+{
+    __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
+    __builtin_amdgcn_wave_barrier();
+    __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
+}
+
 // Row sums as binary64 values, common to the c128, f64 and F_p (Barrett)
 // variants.  E = doubles per entry (2 for complex, 1 for real).  The staged
 // buffer holds [+2A columns][-2A columns], each column n*E doubles.  PFN
@@ -151,21 +161,60 @@ struct RealRows {
     {
         return sp<double>(cols) + (neg ? N * N * E : 0) + N * E * k;
     }
-    __device__ __forceinline__ void seed(uint64_t x)
+    // Row sums at the lane's start index x.  Lane l of an item starts at
+    // x0 + l 2^L with x0 a multiple of nl 2^L, so the Gray codes of the nl
+    // active lanes differ only in bits L-1 .. h, h the highest bit in which
+    // x0 and x0 + (nl - 1) 2^L differ: columns klo = max(L, 1) .. khi = h + 1
+    // (seven for a full item).  Every other column enters every lane's sums
+    // with the sign lane 0 gives it.  The wave therefore forms that common
+    // part once, lane j summing value j of the N*E with coalesced loads that
+    // are all in flight together, and hands it to every lane through LDS;
+    // each lane then adds the varying columns with its own signs, read
+    // through the scalar cache as in the walk.  Against every lane summing
+    // all n columns from the scalar cache (n - 1 dependent rounds of column
+    // loads), this takes about n + 7 N*E vector instructions instead of
+    // n N*E, and seven rounds.  Lanes past nl get no valid sums (their
+    // results are discarded).  lds: SEED_LDS doubles of this wave's own.
+    static constexpr int SEED_LDS = N * E;
+    __device__ __forceinline__ void seed(uint64_t x, uint64_t x0, uint32_t L, uint32_t nl,
+                                         double *lds)
     {
+        constexpr int V = N * E;
+        constexpr int P = (V + WAVE - 1) / WAVE;    // values per lane
+        const int lane = (int)(threadIdx.x & (WAVE - 1));
         const uint64_t g = x ^ (x >> 1);
-        sptr<double> c0 = col(0, false);
+        const uint64_t g0 = x0 ^ (x0 >> 1);
+        int klo = N, khi = N - 1;                   // no varying column
+        if (nl > 1) {
+            const uint64_t xe = x0 + ((uint64_t)(nl - 1) << L);
+            klo = L > 0 ? (int)L : 1;
+            khi = min(64 - __builtin_clzll(x0 ^ xe), N - 1);
+        }
+        const double *c = (const double *)cols;     // the +2A columns, V doubles each
 #pragma unroll
-        for (int i = 0; i < N * E; ++i) r[i] = c0[i];
+        for (int q = 0; q < P; ++q) {
+            const int j0 = lane + q * WAVE;
+            const int j = j0 < V ? j0 : V - 1;
+            double u = c[j];
+#pragma unroll
+            for (int k = 1; k < N; ++k) {
+                const double d = (k >= klo && k <= khi) ? 0.0
+                               : ((g0 >> (k - 1)) & 1) ? -1.0 : 1.0;
+                u = __builtin_fma(d, c[V * k + j], u);
+            }
+            if (j0 < V) lds[j0] = 0.5 * u;
+        }
+        wave_lds_sync();
+#pragma unroll
+        for (int i = 0; i < V; ++i) r[i] = lds[i];
+        wave_lds_sync();                            // read before the next seed writes
 #pragma unroll 1
-        for (int k = 1; k < N; ++k) {
-            const double d = ((g >> (k - 1)) & 1) ? -1.0 : 1.0;
+        for (int k = klo; k <= khi; ++k) {
+            const double d = ((g >> (k - 1)) & 1) ? -0.5 : 0.5;
             sptr<double> ck = col(k, false);
 #pragma unroll
-            for (int i = 0; i < N * E; ++i) r[i] = __builtin_fma(d, ck[i], r[i]);
+            for (int i = 0; i < V; ++i) r[i] = __builtin_fma(d, ck[i], r[i]);
         }
-#pragma unroll
-        for (int i = 0; i < N * E; ++i) r[i] *= 0.5;
     }
     __device__ __forceinline__ void flip(sptr<double> c)
     {
@@ -440,7 +489,9 @@ struct OpsMont {
     {
         return sp<uint32_t>(cols) + (neg ? 3 * N * N : 2 * N * N) + N * k;
     }
-    __device__ __forceinline__ void seed(uint64_t x)
+    // Each lane sums its own start (the item's layout is not used).
+    static constexpr int SEED_LDS = 0;
+    __device__ __forceinline__ void seed(uint64_t x, uint64_t, uint32_t, uint32_t, double *)
     {
         const uint64_t g = x ^ (x >> 1);
         sptr<uint32_t> c0 = aval(0, false);
@@ -581,12 +632,14 @@ __device__ __forceinline__ void group(Ops &S, const char *cols, uint32_t m)
     group_rest(S, m, first_col(S, m + 1));
 }
 
-// One lane: seed at xl, then the 2^c - 1 Gray steps of its chunk.
+// One lane of item `it`: seed at xl, then the 2^c - 1 Gray steps of its
+// chunk (c = it.log2L).
 template <class Ops>
-__device__ __forceinline__ void walk_lane(Ops &S, uint64_t xl, uint32_t c)
+__device__ __forceinline__ void walk_lane(Ops &S, const WaveItem &it, uint64_t xl, double *lds)
 {
+    const uint32_t c = it.log2L;
     const char *cols = S.cols;
-    S.seed(xl);
+    S.seed(xl, it.x0, c, it.nlanes, lds);
     if (c >= 3) {
         const uint32_t G = 1u << (c - 2);      // groups of four steps
         const uint32_t H = G >> 1;             // the group holding j = L/2
@@ -629,12 +682,12 @@ __device__ __forceinline__ double wave_sum(double v)
 
 template <class Ops>
 __device__ __forceinline__ void run_item(const WaveItem &it, const MatDesc &md, const char *stage,
-                                         double *partials, int lane)
+                                         double *partials, int lane, double *lds)
 {
     Ops S;
     S.setup(md, stage + md.stage_off);
     const uint64_t xl = it.x0 + ((uint64_t)lane << it.log2L);
-    walk_lane(S, xl, it.log2L);
+    walk_lane(S, it, xl, lds);
     double a, b;
     S.result(a, b);
     if ((uint32_t)lane >= it.nlanes) { a = 0.0; b = 0.0; }
@@ -919,11 +972,15 @@ void walk_kernel(const WaveItem *items, uint32_t count, uint32_t grab,
                                                      double *partials, unsigned long long *ctr,
                                                      CtrArgs ca)
 {
+    using Ops = typename OpsFor<V, N, KAHAN>::type;
+    constexpr int SL = Ops::SEED_LDS > 0 ? Ops::SEED_LDS : 1;
     __shared__ uint32_t slot[2];
+    __shared__ double seed_lds[WPB * SL];
     const int lane = threadIdx.x & (WAVE - 1);
     stage_in_walk(ca, mats, stage);
     stage = opaque(stage);              // no column load moves above the staging
     BlockClaims bc = block_claims(ctr, ca, slot);
+    double *lds = seed_lds + bc.wave * SL;
     const uint32_t per_run = WPB * grab;
     for_each_run(bc, lane, [&](uint32_t r) __attribute__((always_inline)) {
         r = __builtin_amdgcn_readfirstlane(r);
@@ -931,7 +988,7 @@ void walk_kernel(const WaveItem *items, uint32_t count, uint32_t grab,
         for (uint32_t idx = r * per_run + bc.wave; idx < end; idx += WPB) {
             const WaveItem it = sload(items + idx);
             const MatDesc md = sload(mats + it.mat);
-            run_item<typename OpsFor<V, N, KAHAN>::type>(it, md, stage, partials, lane);
+            run_item<Ops>(it, md, stage, partials, lane, lds);
         }
     });
     finalize_in_walk(ca, mats, partials);
@@ -940,20 +997,21 @@ void walk_kernel(const WaveItem *items, uint32_t count, uint32_t grab,
 // Fused kernel: any mix of c128 / f64 / F_p (Barrett) matrices of order <= NF.
 template <int N, bool KAHAN>
 __device__ __forceinline__ void run_variant(int v, const WaveItem &it, const MatDesc &md,
-                                            const char *stage, double *partials, int lane)
+                                            const char *stage, double *partials, int lane,
+                                            double *lds)
 {
-    if (v == V_C128) run_item<OpsC128<N, KAHAN>>(it, md, stage, partials, lane);
+    if (v == V_C128) run_item<OpsC128<N, KAHAN>>(it, md, stage, partials, lane, lds);
     else if (v == V_F64)    // at the fused kernel's 3 waves f64 has registers for the prefetch
-        run_item<OpsF64<N, KAHAN, (N < PF_MAX ? N : PF_MAX)>>(it, md, stage, partials, lane);
-    else run_item<OpsModp<N>>(it, md, stage, partials, lane);
+        run_item<OpsF64<N, KAHAN, (N < PF_MAX ? N : PF_MAX)>>(it, md, stage, partials, lane, lds);
+    else run_item<OpsModp<N>>(it, md, stage, partials, lane, lds);
 }
 
 template <bool KAHAN, int... Ns>
 __device__ __forceinline__ void run_fused(std::integer_sequence<int, Ns...>, int n, int v,
                                           const WaveItem &it, const MatDesc &md, const char *stage,
-                                          double *partials, int lane)
+                                          double *partials, int lane, double *lds)
 {
-    (void)((n == Ns + 1 ? (run_variant<Ns + 1, KAHAN>(v, it, md, stage, partials, lane), true)
+    (void)((n == Ns + 1 ? (run_variant<Ns + 1, KAHAN>(v, it, md, stage, partials, lane, lds), true)
                         : false) || ...);
 }
 
@@ -965,11 +1023,15 @@ void walk_fused(const WaveItem *items, uint32_t count, uint32_t grab,
                                                     double *partials, unsigned long long *ctr,
                                                     CtrArgs ca)
 {
+    // the largest seed exchange of the orders and variants it runs (c128, NF)
+    constexpr int SL = OpsC128<NF, KAHAN>::SEED_LDS;
     __shared__ uint32_t slot[2];
+    __shared__ double seed_lds[WPB * SL];
     const int lane = threadIdx.x & (WAVE - 1);
     stage_in_walk(ca, mats, stage);
     stage = opaque(stage);              // no column load moves above the staging
     BlockClaims bc = block_claims(ctr, ca, slot);
+    double *lds = seed_lds + bc.wave * SL;
     const uint32_t per_run = WPB * grab;
     for_each_run(bc, lane, [&](uint32_t r) __attribute__((always_inline)) {
         r = __builtin_amdgcn_readfirstlane(r);
@@ -978,7 +1040,7 @@ void walk_fused(const WaveItem *items, uint32_t count, uint32_t grab,
             const WaveItem it = sload(items + idx);
             const MatDesc md = sload(mats + it.mat);
             run_fused<KAHAN>(std::make_integer_sequence<int, NF>{}, md.n, md.variant, it, md,
-                             stage, partials, lane);
+                             stage, partials, lane, lds);
         }
     });
     finalize_in_walk(ca, mats, partials);
