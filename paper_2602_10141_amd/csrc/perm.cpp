@@ -230,10 +230,14 @@ int latency_log2_chunk(const perm_ctx *ctx, int variant, int n, uint64_t nmats, 
     const int field = variant == V_MONT ? PERM_MODP : variant;
     auto it = ctx->tune.find({field, n});
     if (it != ctx->tune.end() && it->second.log2_chunk > 0) return c0;   // the table decides
-    // two waves per SIMD already issue close to every cycle (four independent
-    // product chains per lane), so a round is two waves per SIMD at most
+    // A round is two waves per SIMD for c128 and F_p: with four independent
+    // chains of complex or modular products per lane two waves already issue
+    // close to every cycle.  The f64 walk, a third of their instructions per
+    // step, needs four (one matrix of order 26: 2^7-index lanes at four waves
+    // walked 17% faster than the 2^8 that two waves per SIMD suggest).
+    const int per_simd = variant == V_F64 ? 4 : 2;
     const uint64_t slots =
-        (uint64_t)std::min(std::max(blocks_per_cu, 1), 2) * ctx->num_cus * (BLOCK / WAVE);
+        (uint64_t)std::min(std::max(blocks_per_cu, 1), per_simd) * ctx->num_cus * (BLOCK / WAVE);
     const uint64_t T = 1ull << (n - 1);
     auto items = [&](int c) { return nmats * (T >= (64ull << c) ? T >> (6 + c) : 1ull); };
     if (items(c0) >= slots) return c0;

@@ -181,7 +181,10 @@ struct RealRows {
     {
         constexpr int V = N * E;
         constexpr int P = (V + WAVE - 1) / WAVE;    // values per lane
-        const int lane = (int)(threadIdx.x & (WAVE - 1));
+        int lane = (int)(threadIdx.x & (WAVE - 1));
+        // a fresh value per call, so that the addresses derived from it are
+        // formed here and not kept (or spilled) across the walk
+        asm volatile("" : "+v"(lane));
         const uint64_t g = x ^ (x >> 1);
         const uint64_t g0 = x0 ^ (x0 >> 1);
         int klo = N, khi = N - 1;                   // no varying column
