@@ -127,10 +127,10 @@ struct CtrArgs {                 // kernel argument (by value)
     uint64_t base[CTR_GROUPS];
     uint32_t groups;
     uint32_t runs;               // runs of items, computed on the host
-    char *fin_out;               // one-block launch: stage fin_nmats matrices
-    const char *fin_src;         //   from fin_src, walk, finalize them into
-    uint32_t fin_nmats;          //   fin_out (else 0)
-    uint32_t pad;
+    char *fin_out;               // fin_nmats > 0: every block stages matrices
+    const char *fin_src;         //   0 .. fin_nmats from fin_src before walking;
+    uint32_t fin_nmats;          //   a one-block launch with fin_out also
+    uint32_t pad;                //   finalizes them into fin_out
 };
 
 // Items are walked in runs of (BLOCK / WAVE) * grab consecutive items
@@ -138,10 +138,12 @@ struct CtrArgs {                 // kernel argument (by value)
 // run: block b walks run b first, then claims runs with one atomic each
 // (several items per run keep tiny items from making the claims the
 // bottleneck).  `state` holds the counters' values before the launch and
-// is advanced past it.  With fin_nmats > 0 (only for grid_blocks == 1 and the
-// call's matrices being all of d_mats[0 .. fin_nmats)), the block also does
-// launch_stage's work (from fin_src) first and launch_finalize's work (into
-// fin_out) last, and the caller launches neither.
+// is advanced past it.  With fin_nmats > 0 (the call's matrices being all of
+// d_mats[0 .. fin_nmats)) every block first does launch_stage's work from
+// fin_src, and the caller does not launch it: the blocks write the same bytes
+// and each reads only after its own barrier.  With fin_out as well (only for
+// grid_blocks == 1) the block also does launch_finalize's work into fin_out
+// last, and the caller does not launch that either.
 int launch_walk(int variant, int n, bool kahan, bool fused, int nmax_fused,
                 const WaveItem *d_items, uint32_t count, uint32_t grab, const MatDesc *d_mats,
                 const void *stage, double *partials, unsigned long long *ctr,

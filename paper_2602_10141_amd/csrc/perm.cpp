@@ -592,9 +592,23 @@ int execute(perm_ctx *ctx, Plan &pl, const void *src, void *out, size_t out_slot
         ++walks;
         last = (int)q;
     }
-    // a call that is one walk of one block stages and finalizes in that block
+    // A call that is one walk of one block stages and finalizes in that
+    // block.  A short walk (at most 2^26 terms, about 0.2 ms) over a few
+    // small matrices -- a single permanent of order up to 27 -- stages them
+    // in every block instead of in a launch of its own: such calls are
+    // bound by the host's launches, which cost more than the blocks' copies
+    // of at most 16 entries per thread cost the device (one U(16)..U(20) or
+    // O(20) per call 11-14% faster).
     const bool one_block = walks == 1 && shape[last].grid == 1;
-    if (!one_block)
+    size_t entries = 0;
+    uint64_t terms = 0;
+    for (const MatDesc &d : pl.mats) {
+        entries += (size_t)d.n * d.n;
+        terms += d.n > 0 ? 1ull << (d.n - 1) : 0;
+    }
+    const bool block_stage = one_block || (walks == 1 && pl.mats.size() <= 4 &&
+                                           entries <= 16 * BLOCK && terms <= (1ull << 26));
+    if (!block_stage)
         HIPCHK((hipError_t)launch_stage(d_mats, (int)pl.mats.size(), src, ctx->stage.p, s));
     for (size_t q = 0; q < pl.groups.size(); ++q) {
         const Group &g = pl.groups[q];
@@ -622,9 +636,9 @@ int execute(perm_ctx *ctx, Plan &pl, const void *src, void *out, size_t out_slot
                                        d_items + g.first_item, g.count, shape[q].grab, d_mats,
                                        ctx->stage.p, (double *)ctx->partials.p,
                                        (unsigned long long *)ctx->ctr.p, &ctx->ctr_state,
-                                       shape[q].grid, s, one_block ? src : nullptr,
+                                       shape[q].grid, s, block_stage ? src : nullptr,
                                        one_block ? out : nullptr,
-                                       one_block ? (int)pl.mats.size() : 0));
+                                       block_stage ? (int)pl.mats.size() : 0));
         if (prof) {
             HIPCHK(hipEventRecord(ev.second, s));
             std::lock_guard<std::mutex> lk(ctx->prof_mu);
@@ -877,13 +891,12 @@ extern "C" int perm_c128_noalloc(perm_ctx *ctx, const double *A, int n, double *
         const MatDesc *d_mats = (const MatDesc *)(base + L.mat);
         void *stage = base + L.stage;
         double *partials = (double *)(base + L.partials);
-        if (!one_block) HIPCHK((hipError_t)launch_stage(d_mats, 1, A, stage, s));
+        // every block stages the matrix (at most 32 x 32 entries)
         CtrState st{};                      // the plan kernel zeroed the counters
         HIPCHK((hipError_t)launch_walk(V_C128, n, kahan, false, 0,
                                        (const WaveItem *)(base + L.items), cnt, grab, d_mats, stage,
                                        partials, (unsigned long long *)(base + L.ctr), &st, grid, s,
-                                       one_block ? A : nullptr, one_block ? out : nullptr,
-                                       one_block ? 1 : 0));
+                                       A, one_block ? out : nullptr, 1));
         if (!one_block) HIPCHK((hipError_t)launch_finalize(d_mats, 1, partials, out, s));
     }
     return end_call(ctx, s);

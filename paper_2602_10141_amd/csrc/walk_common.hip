@@ -67,7 +67,7 @@ int launch_walk(int variant, int n, bool kahan, bool fused, int nmax_fused, cons
     WalkFn f = pick(variant, n, kahan, fused, nmax_fused);
     if (!f || grab < 1 || !state) return (int)hipErrorInvalidValue;
     if (grid_blocks < 1) grid_blocks = 1;
-    if (fin_nmats < 0 || (fin_nmats > 0 && (grid_blocks != 1 || !fin_out || !fin_src)))
+    if (fin_nmats < 0 || (fin_nmats > 0 && !fin_src) || (fin_out && (grid_blocks != 1 || !fin_nmats)))
         return (int)hipErrorInvalidValue;
     const uint64_t per_run = (uint64_t)(BLOCK / WAVE) * grab;
     const uint64_t runs = ((uint64_t)count + per_run - 1) / per_run;

@@ -938,12 +938,15 @@ __device__ __forceinline__ void for_each_run(BlockClaims &bc, int lane, F &&walk
     for (uint32_t r = blockIdx.x; r < bc.runs; r = claims ? bc.next(lane) : bc.runs) walk_run(r);
 }
 
-// A launch that is the whole call in one block (a single small matrix, or a
-// few tiny ones) stages its matrices itself before walking and finalizes
-// them afterwards, saving two launches.  The block's vector stores complete
-// before the barrier; the scalar cache starts every dispatch empty and no
-// scalar load touches the staged lines before they are written, so the
-// walk's column loads read the new values (from this XCD's L2).
+// A launch over a few small matrices stages them in every block before
+// walking, saving the stage launch; one that is the whole call in one block
+// (a single small matrix, or a few tiny ones) also finalizes them afterwards,
+// saving the finalize launch.  The blocks write the same bytes.  A block's
+// vector stores complete before its barrier, and its waves read the staged
+// lines only after that barrier, from this XCD's L2, which then holds the
+// block's own write or another block's identical one; the scalar and vector
+// L1 caches start every dispatch empty, so a line they hold was fetched
+// after some block of the XCD had written it.
 __device__ __forceinline__ void stage_in_walk(const CtrArgs &ca, const MatDesc *mats,
                                               const char *stage)
 {
@@ -956,7 +959,7 @@ __device__ __forceinline__ void stage_in_walk(const CtrArgs &ca, const MatDesc *
 __device__ __forceinline__ void finalize_in_walk(const CtrArgs &ca, const MatDesc *mats,
                                                  const double *partials)
 {
-    if (!ca.fin_nmats) return;
+    if (!ca.fin_nmats || !ca.fin_out) return;
     __shared__ double sa[256], sb[256];
     __shared__ unsigned long long su[256];
     for (uint32_t m = 0; m < ca.fin_nmats; ++m) {
