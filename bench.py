@@ -654,15 +654,16 @@ def _serve_run(P, ctx, reqs, rate, seed, slice_us):
 
     sub = th.Thread(target=submitter)
     sub.start()
-    vals, lats = [None] * len(reqs), [0.0] * len(reqs)
+    vals, lats, phases = [None] * len(reqs), [0.0] * len(reqs), [None] * len(reqs)
     try:
         for i in range(len(reqs)):
             while tickets[i] is None:
                 if errors:
                     raise RuntimeError(f"submitting request {i} failed") from errors[0]
                 time.sleep(0.0002)
-            vals[i], lats[i] = srv.wait(tickets[i][0], tickets[i][1], timeout_s=120,
-                                        with_latency=True)
+            vals[i], phases[i] = srv.wait(tickets[i][0], tickets[i][1], timeout_s=120,
+                                          with_times=True)
+            lats[i] = phases[i]["latency_us"]
     except BaseException:
         srv.close()
         sub.join()
@@ -671,6 +672,10 @@ def _serve_run(P, ctx, reqs, rate, seed, slice_us):
     wall = time.perf_counter() - t0
     st = srv.stats()
     srv.close()
+    # where the latency went: waiting for admission, admitted but not yet in
+    # a launched slice, and from the first launch to the result
+    st["phases"] = {k: _pcts(np.array([ph[k] for ph in phases]))
+                    for k in ("queued_us", "admitted_us", "running_us")}
     return vals, np.array(lats), wall, st
 
 
@@ -717,6 +722,7 @@ def sub_serve(P, ctx, args, loads=(0.5, 0.7, 0.9)):
                                  "terms_per_s": terms / wall, **_pcts(lats),
                                  "slices": st["slices"], "busy_s": st["busy_s"],
                                  "items": st["items"], "rate": st["rate"],
+                                 "phases": st["phases"],
                                  "geodesic": _pcts(lats[cls == "geodesic"]),
                                  "schur": _pcts(lats[cls == "schur"])}}
         ref = vals
@@ -727,6 +733,7 @@ def sub_serve(P, ctx, args, loads=(0.5, 0.7, 0.9)):
             result[f"load_{f}"] = {"wall_s": w, "offered_per_s": f * sat_rate, **_pcts(l),
                                    "slices": s2["slices"], "busy_s": s2["busy_s"],
                                    "items": s2["items"], "rate": s2["rate"],
+                                   "phases": s2["phases"],
                                    "geodesic": _pcts(l[cls == "geodesic"]),
                                    "schur": _pcts(l[cls == "schur"])}
         # every Schur residue is 0 for even n; geodesic perms are real and |.| <= 1

@@ -338,6 +338,20 @@ int perm_srv_poll(perm_srv *srv, uint64_t ticket, void *out16, int *done, double
 /* Block until the ticket finishes or timeout_s passes (then *done = 0). */
 int perm_srv_wait(perm_srv *srv, uint64_t ticket, double timeout_s, void *out16, int *done,
                   double *latency_us);
+/* Where a request's time went, in microseconds of host time: queued_us from
+ * submit to admission (device memory and a descriptor slot granted),
+ * admitted_us from admission to the launch of the first slice carrying its
+ * work, running_us from that launch to the result becoming visible on the
+ * host; latency_us is their sum.  A phase the request never reached (it
+ * was cancelled or failed before) is 0 and the time goes to the last phase
+ * it reached. */
+typedef struct {
+    double queued_us, admitted_us, running_us, latency_us;
+} perm_srv_times;
+/* perm_srv_wait, reporting the phases of the request's latency in *times
+ * (optional, filled once *done = 1). */
+int perm_srv_wait_times(perm_srv *srv, uint64_t ticket, double timeout_s, void *out16, int *done,
+                        perm_srv_times *times);
 int perm_srv_cancel(perm_srv *srv, uint64_t ticket);
 int perm_srv_get_stats(perm_srv *srv, perm_srv_stats *out);
 /* Stop accepting, finish or cancel everything, join the worker. */

@@ -93,6 +93,7 @@ struct Req {
     int status = PERM_OK;
     bool cancel = false;
     double t_submit = 0, t_done = 0;
+    double t_admit = 0, t_start = 0;     // admitted; first slice with its items launched
     // device placement (admitted)
     size_t off = 0, bytes = 0;
     int slot = -1;                       // row of the device MatDesc table
@@ -227,6 +228,7 @@ std::vector<uint64_t> admit_locked(perm_srv *S)
         r.slot = S->free_slots.back();
         S->free_slots.pop_back();
         r.state = R_ADMITTED;
+        r.t_admit = now_us();
         S->admitted.push_back(t);
         S->st.admitted++;
         now.push_back(t);
@@ -632,6 +634,10 @@ int run_slice(perm_srv *S, bool *launched)
         S->st.slices++;
         S->st.items += items.size();
         for (uint64_t t : fresh) S->reqs.at(t).matrix.clear();
+        for (uint64_t t : sl.touched) {
+            Req &r = S->reqs.at(t);
+            if (r.t_start == 0) r.t_start = sl.launch_us;
+        }
     }
     S->cur ^= 1;
     S->prev_done_valid = true;
@@ -795,8 +801,8 @@ extern "C" int perm_srv_submit(perm_srv *S, const perm_item *item, const void *m
     return PERM_OK;
 }
 
-extern "C" int perm_srv_poll(perm_srv *S, uint64_t ticket, void *out16, int *done,
-                             double *latency_us)
+static int poll_impl(perm_srv *S, uint64_t ticket, void *out16, int *done, double *latency_us,
+                     perm_srv_times *times)
 {
     if (!S || !done) return fail(PERM_EINVAL, "NULL argument");
     std::lock_guard<std::mutex> lk(S->mu);
@@ -811,12 +817,21 @@ extern "C" int perm_srv_poll(perm_srv *S, uint64_t ticket, void *out16, int *don
     const int st = r.status;
     if (out16 && st == PERM_OK) std::memcpy(out16, r.result, 16);
     if (latency_us) *latency_us = r.t_done - r.t_submit;
+    if (times) {
+        // phases end where the next begins; a phase never reached ends at t_done
+        const double a = r.t_admit > 0 ? r.t_admit : r.t_done;
+        const double b = r.t_start > 0 ? r.t_start : r.t_done;
+        times->queued_us = a - r.t_submit;
+        times->admitted_us = b - a;
+        times->running_us = r.t_done - b;
+        times->latency_us = r.t_done - r.t_submit;
+    }
     if (!referenced) S->reqs.erase(it);
     return st;
 }
 
-extern "C" int perm_srv_wait(perm_srv *S, uint64_t ticket, double timeout_s, void *out16, int *done,
-                             double *latency_us)
+static int wait_impl(perm_srv *S, uint64_t ticket, double timeout_s, void *out16, int *done,
+                     double *latency_us, perm_srv_times *times)
 {
     if (!S || !done) return fail(PERM_EINVAL, "NULL argument");
     {
@@ -828,7 +843,25 @@ extern "C" int perm_srv_wait(perm_srv *S, uint64_t ticket, double timeout_s, voi
             return it == S->reqs.end() || it->second.state == R_DONE;
         });
     }
-    return perm_srv_poll(S, ticket, out16, done, latency_us);
+    return poll_impl(S, ticket, out16, done, latency_us, times);
+}
+
+extern "C" int perm_srv_poll(perm_srv *S, uint64_t ticket, void *out16, int *done,
+                             double *latency_us)
+{
+    return poll_impl(S, ticket, out16, done, latency_us, nullptr);
+}
+
+extern "C" int perm_srv_wait(perm_srv *S, uint64_t ticket, double timeout_s, void *out16, int *done,
+                             double *latency_us)
+{
+    return wait_impl(S, ticket, timeout_s, out16, done, latency_us, nullptr);
+}
+
+extern "C" int perm_srv_wait_times(perm_srv *S, uint64_t ticket, double timeout_s, void *out16,
+                                   int *done, perm_srv_times *times)
+{
+    return wait_impl(S, ticket, timeout_s, out16, done, nullptr, times);
 }
 
 extern "C" int perm_srv_cancel(perm_srv *S, uint64_t ticket)

@@ -45,6 +45,11 @@ class perm_srv_cfg(ctypes.Structure):
                 ("flags", ctypes.c_uint)]
 
 
+class perm_srv_times(ctypes.Structure):
+    _fields_ = [("queued_us", ctypes.c_double), ("admitted_us", ctypes.c_double),
+                ("running_us", ctypes.c_double), ("latency_us", ctypes.c_double)]
+
+
 class perm_srv_stats(ctypes.Structure):
     _fields_ = [("submitted", ctypes.c_uint64), ("admitted", ctypes.c_uint64),
                 ("completed", ctypes.c_uint64), ("failed", ctypes.c_uint64),
@@ -90,6 +95,7 @@ _SIGS = {
     "perm_srv_submit": ([_P, _P, _P, _P], _I),
     "perm_srv_poll": ([_P, _U64, _P, _P, _P], _I),
     "perm_srv_wait": ([_P, _U64, _D, _P, _P, _P], _I),
+    "perm_srv_wait_times": ([_P, _U64, _D, _P, _P, _P], _I),
     "perm_srv_cancel": ([_P, _U64], _I),
     "perm_srv_get_stats": ([_P, _P], _I),
     "perm_srv_destroy": ([_P], None),
@@ -504,18 +510,27 @@ class Server:
             raise PermError(rc, perm_last_error() if rc != PERM_ECANCELED else "cancelled")
         return (True, self._decode(it, buf.raw)) if done.value else (False, None)
 
-    def wait(self, ticket, it, timeout_s=60.0, with_latency=False):
-        """Result of a ticket (and its submit-to-result latency in us if asked)."""
+    def wait(self, ticket, it, timeout_s=60.0, with_latency=False, with_times=False):
+        """Result of a ticket; with_latency: (result, submit-to-result us);
+        with_times: (result, dict of the latency's phases in us, as
+        perm_srv_wait_times reports them)."""
         buf = ctypes.create_string_buffer(16)
         done = ctypes.c_int()
         lat = ctypes.c_double()
-        rc = lib().perm_srv_wait(self.ptr, ticket, float(timeout_s), buf, ctypes.byref(done),
-                                 ctypes.byref(lat))
+        tm = perm_srv_times()
+        if with_times:
+            rc = lib().perm_srv_wait_times(self.ptr, ticket, float(timeout_s), buf,
+                                           ctypes.byref(done), ctypes.byref(tm))
+        else:
+            rc = lib().perm_srv_wait(self.ptr, ticket, float(timeout_s), buf, ctypes.byref(done),
+                                     ctypes.byref(lat))
         if rc != PERM_OK:
             raise PermError(rc, perm_last_error() if rc != PERM_ECANCELED else "cancelled")
         if not done.value:
             raise TimeoutError(f"ticket {ticket} not done after {timeout_s} s")
         v = self._decode(it, buf.raw)
+        if with_times:
+            return v, {k: getattr(tm, k) for k, _ in perm_srv_times._fields_}
         return (v, lat.value) if with_latency else v
 
     def cancel(self, ticket):

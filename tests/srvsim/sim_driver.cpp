@@ -8,6 +8,7 @@
 
 #include <atomic>
 #include <chrono>
+#include <cmath>
 #include <cstdio>
 #include <cstdlib>
 #include <cstring>
@@ -107,11 +108,25 @@ int main()
             unsigned char out[16];
             int done = 0;
             double lat = 0;
-            const int rc = perm_srv_wait(S, tickets[i], 30.0, out, &done, &lat);
+            perm_srv_times tm{};
+            // odd requests report the phases of their latency
+            const int rc = (i & 1) ? perm_srv_wait_times(S, tickets[i], 30.0, out, &done, &tm)
+                                   : perm_srv_wait(S, tickets[i], 30.0, out, &done, &lat);
             if (!done) {
                 fprintf(stderr, "request %zu (n=%d) not done after 30 s\n", i, reqs[i].it.n);
                 fflush(stderr);
                 _Exit(3);
+            }
+            if (i & 1) {
+                const double sum = tm.queued_us + tm.admitted_us + tm.running_us;
+                const bool unstarted = rc == PERM_ECANCELED && tm.running_us == 0;
+                if (tm.queued_us < 0 || tm.admitted_us < 0 || tm.running_us < 0 ||
+                    std::fabs(sum - tm.latency_us) > 1e-6 * std::max(1.0, tm.latency_us) ||
+                    (rc == PERM_OK && tm.admitted_us + tm.running_us <= 0 && !unstarted)) {
+                    fprintf(stderr, "request %zu: phases %.3f %.3f %.3f us, latency %.3f us\n", i,
+                            tm.queued_us, tm.admitted_us, tm.running_us, tm.latency_us);
+                    ++wrong;
+                }
             }
             if (cancel_every && i % cancel_every == 0 && rc == PERM_ECANCELED) continue;
             if (faults && rc == PERM_EDEVICE) {

@@ -59,6 +59,28 @@ def test_results_match_batch_bitwise(P, ctx, oracle_lib):
             assert abs(v - 1) < 1e-14
 
 
+def test_latency_phases(P, ctx):
+    """perm_srv_wait_times: the same results, and the phases of each request's
+    latency are non-negative and add up to it; under a budget that admits
+    one request at a time, the later requests spend time queued."""
+    reqs = mixed_requests()
+    items, data = P.pack_matrices(reqs)
+    want = P.batch_values(items, P.perm_batch(ctx, items, data))
+    srv = P.Server(ctx, max_inflight=1, slice_us=500)
+    try:
+        tickets = [srv.submit(A, f, p) for A, f, p in reqs]
+        got = [srv.wait(t, it, timeout_s=60, with_times=True) for t, it in tickets]
+    finally:
+        srv.close()
+    assert [v for v, _ in got] == want
+    for _, ph in got:
+        assert min(ph["queued_us"], ph["admitted_us"], ph["running_us"]) >= 0
+        assert abs(ph["queued_us"] + ph["admitted_us"] + ph["running_us"] - ph["latency_us"]) \
+            <= 1e-6 * max(1.0, ph["latency_us"])
+        assert ph["running_us"] > 0
+    assert got[-1][1]["queued_us"] > got[0][1]["queued_us"]
+
+
 def test_alone_equals_in_mix(P, ctx):
     A = E.cycle_geodesic(17, 0.3)
     srv = P.Server(ctx)
