@@ -153,6 +153,26 @@ def _threads():
     return min(HOST_THREADS, os.cpu_count() or 1)
 
 
+def _run_threads(work, count):
+    """work(0) .. work(count - 1) on threads of their own; the first
+    exception a worker raised is raised here once all have ended."""
+    errors = []
+
+    def run(i):
+        try:
+            work(i)
+        except BaseException as e:
+            errors.append(e)
+
+    ths = [threading.Thread(target=run, args=(i,)) for i in range(count)]
+    for th in ths:
+        th.start()
+    for th in ths:
+        th.join()
+    if errors:
+        raise errors[0]
+
+
 def cpu_baseline_schur(n, primes, seconds=12.0):
     """Oracle Ryser mod p on S_n, bounded prefix, all host threads."""
     from oracle import crt, native
@@ -170,11 +190,7 @@ def cpu_baseline_schur(n, primes, seconds=12.0):
         done.append(per_thread - 1)
 
     t = time.perf_counter()
-    ths = [threading.Thread(target=work, args=(i,)) for i in range(threads)]
-    for th in ths:
-        th.start()
-    for th in ths:
-        th.join()
+    _run_threads(work, threads)
     dt = time.perf_counter() - t
     ryser_subsets_per_s = sum(done) / dt
     # one permanent = 2^n Ryser subsets on the CPU = 2^(n-1) Glynn terms in the metric
@@ -223,11 +239,7 @@ def cpu_baseline_many(mats, field, seconds=5.0, label=None):
             _oracle_perm(*mats[i])
             done[w] += 1
 
-    ths = [threading.Thread(target=work, args=(w,)) for w in range(threads)]
-    for th in ths:
-        th.start()
-    for th in ths:
-        th.join()
+    _run_threads(work, threads)
     dt = time.perf_counter() - t0
     return _with_host({
         "value": sum(done) / dt, "unit": "perms/s", "cores": threads, "kind": "oracle",
@@ -260,11 +272,7 @@ def cpu_baseline_single(A, seconds=2.0):
             native.ryser_c128(A)
             counts[w] += 1
 
-    ths = [threading.Thread(target=work, args=(w,)) for w in range(threads)]
-    for th in ths:
-        th.start()
-    for th in ths:
-        th.join()
+    _run_threads(work, threads)
     dt = time.perf_counter() - t0
     return _with_host({
         "value": sum(counts) / dt, "unit": "perms/s", "cores": threads, "kind": "oracle",
@@ -768,8 +776,8 @@ def bench_serve(P, ctx, args):
 
 def bench_default(P, ctx, args):
     """The headline line: S_28 over three primes is `value`; configs 1, 3,
-    4 and 5 follow as sub-records, each with its median, roofline and
-    oracle baseline."""
+    4 and 5 and single matrices of orders 20..36 follow as sub-records, each
+    with its timing, roofline and oracle baseline."""
     progress("S_28 over three primes")
     line = bench_schur(P, ctx, args)
     cfg = {}
@@ -789,6 +797,8 @@ def bench_default(P, ctx, args):
                                              cpu_label="ragged GUE/GOE/Ginibre")
     progress("config 5: serving stream")
     cfg["serve_stream_530"] = sub_serve(P, ctx, args)
+    progress("single matrices of orders 20..36")
+    cfg["single_matrix_orders_20_36"] = sub_sizes(P, ctx, args)
     line["configs"] = cfg
     return line
 
@@ -872,31 +882,59 @@ def bench_stats(P, ctx, args):
             "runs": runs}
 
 
-def bench_sizes(P, ctx, args):
+def cpu_baseline_range(A, field, seconds=5.0):
+    """The oracle's Ryser sum over a bounded range of subsets of one matrix,
+    split over the host threads (disjoint ranges), scaled to Glynn-term
+    equivalents (2^n Ryser subsets per permanent against 2^(n-1) terms)."""
+    from oracle import native
+    n = A.shape[0]
+    threads = _threads()
+    t = time.perf_counter()
+    native.ryser_float_range(A, 1, 1 + (1 << 16))
+    rate1 = (1 << 16) / (time.perf_counter() - t)
+    # subsets 1 .. 2^n - 1 (the empty set contributes nothing)
+    per_thread = int(min(((1 << n) - 1) // threads, max(1 << 16, rate1 * seconds)))
+
+    def work(i):
+        native.ryser_float_range(A, 1 + i * per_thread, 1 + (i + 1) * per_thread)
+
+    t = time.perf_counter()
+    _run_threads(work, threads)
+    dt = time.perf_counter() - t
+    return _with_host({
+        "value": per_thread * threads / dt / 2, "unit": "subset-terms/s (Glynn-term equivalents)",
+        "cores": threads, "kind": "oracle", "value_1thread": rate1 / 2,
+        "sample": f"oracle Ryser ({field}) on one matrix of order {n}: {per_thread} subsets per "
+                  f"thread, {threads} threads in {dt:.1f} s; rate scaled to 2^{n - 1} terms "
+                  f"per permanent"})
+
+
+def sub_sizes(P, ctx, args):
     """One matrix per call across the orders of the headline metric: Haar
     U(n) (c128) and O(n) (f64) for n = 20..36 and the Schur matrix S_n mod
     one prime (F_p) for n = 22..36.  Per case: the call's time and terms/s
-    and the walk kernel's fraction of the FP64 VALU peak.  Single calls of
-    orders 16..27 use the latency partition (shorter wave items, so that one
-    matrix occupies the device); from order 28 the batch partition already
-    does."""
+    and the walk kernel's fraction of the FP64 VALU peak; the record's
+    roofline is over all cases (their algorithmic instructions over their
+    summed walk time).  Single calls of orders 16..27 use the latency
+    partition (shorter wave items, so that one matrix occupies the device);
+    from order 28 the batch partition already does."""
     import torch
     from paper_2602_10141_amd import ensembles as E
     cases = ([("c128", n) for n in (20, 22, 24, 26, 28, 30, 32, 34, 36)] +
              [("f64", n) for n in (20, 22, 24, 26, 28, 32, 36)] +
              [("modp", n) for n in (22, 24, 26, 28, 30, 32, 34, 36)])
-    rows, tot_terms, tot_s = [], 0, 0.0
+    rows, tot_terms, tot_s, tot_ops, tot_walk_ms = [], 0, 0.0, 0.0, 0.0
     for field, n in cases:
         if field == "c128":
             A = torch.from_numpy(E.haar_unitary(n, E.rng(50, n))).cuda()
-            fn = lambda: P.perm_c128(ctx, A)
+            fn = lambda: P.perm_c128(ctx, A)      # noqa: E731
         elif field == "f64":
             A = torch.from_numpy(E.haar_orthogonal(n, E.rng(51, n))).cuda()
-            fn = lambda: P.perm_f64(ctx, A)
+            fn = lambda: P.perm_f64(ctx, A)       # noqa: E731
         else:
             p = P.perm_schur_primes(n)[0]
             A = torch.from_numpy(P.perm_schur_residues(n, p).astype(np.int32)).cuda()
-            fn = lambda: P.perm_modp(ctx, A, p)
+            fn = lambda: P.perm_modp(ctx, A, p)   # noqa: E731
         terms = 1 << (n - 1)
         reps = max(1, int(4e9 / terms))
         fn()
@@ -910,15 +948,30 @@ def bench_sizes(P, ctx, args):
         dt = (time.perf_counter() - t0) / reps
         walk_ms, launches = P.perm_prof_read(ctx)
         P.perm_prof_enable(ctx, False)
+        ops = terms * ops_per_term(field, n)
         rows.append({"field": field, "n": n, "ms": dt * 1e3, "terms_per_s": terms / dt,
-                     "roofline": roofline(terms * ops_per_term(field, n), walk_ms, launches)})
+                     "roofline": roofline(ops, walk_ms, launches)})
         tot_terms += terms
         tot_s += dt
-    return {"metric": METRIC, "value": tot_terms / tot_s, "unit": "subset-terms/s",
-            "ms_per_step": tot_s * 1e3, "dtype": "c128+f64+f64(F_p)",
-            "config": {"workload": "single_matrix_orders_20_36",
-                       "cases": [f"{f}{n}" for f, n in cases]},
-            "runs": rows}
+        tot_ops += ops
+        tot_walk_ms += walk_ms / max(launches, 1)
+    rec = {"workload": "single_matrix_orders_20_36", "value": tot_terms / tot_s,
+           "unit": "subset-terms/s", "dtype": "c128+f64", "cases": [f"{f}{n}" for f, n in cases],
+           "roofline": roofline(tot_ops / len(cases), tot_walk_ms, len(cases)), "runs": rows}
+    if not args.no_cpu:
+        rec["cpu_baseline"] = cpu_baseline_range(E.haar_unitary(28, E.rng(50, 28)), "c128")
+    return rec
+
+
+def bench_sizes(P, ctx, args):
+    rec = sub_sizes(P, ctx, args)
+    line = {"metric": METRIC, "value": rec["value"], "unit": "subset-terms/s",
+            "ms_per_step": sum(r["ms"] for r in rec["runs"]), "dtype": "c128+f64",
+            "config": {"workload": rec["workload"], "cases": rec["cases"]},
+            "roofline": rec["roofline"], "runs": rec["runs"]}
+    if "cpu_baseline" in rec:
+        line["cpu_baseline"] = rec["cpu_baseline"]
+    return line
 
 
 def bench_dft(P, ctx, args):

@@ -85,5 +85,14 @@ def test_default_workload_is_the_headline_with_sub_records():
     import inspect
     src = inspect.getsource(bench.bench_default)
     for key in ("single_haar_u14_c128", "haar_u20_c128_50000", "haar_o20_f64_50000",
-                "ragged_gaussian_10000", "serve_stream_530"):
+                "ragged_gaussian_10000", "serve_stream_530", "single_matrix_orders_20_36"):
         assert key in src
+
+
+def test_range_baseline_is_scaled_to_glynn_terms():
+    """The single-matrix baseline: disjoint subset ranges on every host
+    thread, reported per Glynn term (half a Ryser subset)."""
+    from paper_2602_10141_amd import ensembles as E
+    r = bench.cpu_baseline_range(E.haar_unitary(20, E.rng(90, 0)), "c128", seconds=0.1)
+    assert r["kind"] == "oracle" and r["value"] > 0 and r["cores"] >= 1
+    assert r["unit"].startswith("subset-terms/s") and "order 20" in r["sample"]
