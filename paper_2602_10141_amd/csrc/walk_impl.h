@@ -174,17 +174,21 @@ struct RealRows {
     // all n columns from the scalar cache (n - 1 dependent rounds of column
     // loads), this takes about n + 7 N*E vector instructions instead of
     // n N*E, and seven rounds.  Lanes past nl get no valid sums (their
-    // results are discarded).  lds: SEED_LDS doubles of this wave's own.
+    // results are discarded).  lds_block: the block's exchange area, `stride`
+    // (at least SEED_LDS) doubles per wave.
     static constexpr int SEED_LDS = N * E;
     __device__ __forceinline__ void seed(uint64_t x, uint64_t x0, uint32_t L, uint32_t nl,
-                                         double *lds)
+                                         double *lds_block, int stride)
     {
         constexpr int V = N * E;
         constexpr int P = (V + WAVE - 1) / WAVE;    // values per lane
-        int lane = (int)(threadIdx.x & (WAVE - 1));
-        // a fresh value per call, so that the addresses derived from it are
-        // formed here and not kept (or spilled) across the walk
-        asm volatile("" : "+v"(lane));
+        // The lane and wave numbers are formed afresh in every seed: values
+        // derived from them and kept across the walk loop would cost registers
+        // the loop needs (they were spilled there).
+        int tid = (int)threadIdx.x;
+        asm volatile("" : "+v"(tid));
+        const int lane = tid & (WAVE - 1);
+        double *lds = lds_block + __builtin_amdgcn_readfirstlane(tid / WAVE) * stride;
         const uint64_t g = x ^ (x >> 1);
         const uint64_t g0 = x0 ^ (x0 >> 1);
         int klo = N, khi = N - 1;                   // no varying column
@@ -266,6 +270,7 @@ struct PfC128 {
                            : N == 21 ? 40
                            : (N <= 23 || N == 26) ? 32
                            : N <= 28 ? 16
+                           : N == 29 ? 32
                            : N <= 31 ? PF_MAX
                            : 16;
 };
@@ -415,9 +420,16 @@ __device__ __forceinline__ double reduce_to_range(double v, double p, double pin
     return r;
 }
 
+// F_p prefetches the whole column up to 40 entries, 32 at the orders where
+// 40 left the walk loop spilling registers (43, 46, 47).
 template <int N>
-struct OpsModp : RealRows<N, 1, (N < PF_MAX ? N : PF_MAX)> {
-    using RealRows<N, 1, (N < PF_MAX ? N : PF_MAX)>::r;
+struct PfModp {
+    static constexpr int n = (N == 43 || N == 46 || N == 47) ? 32 : (N < PF_MAX ? N : PF_MAX);
+};
+
+template <int N>
+struct OpsModp : RealRows<N, 1, PfModp<N>::n> {
+    using RealRows<N, 1, PfModp<N>::n>::r;
     double s;
     double p, pinv;
 
@@ -494,7 +506,7 @@ struct OpsMont {
     }
     // Each lane sums its own start (the item's layout is not used).
     static constexpr int SEED_LDS = 0;
-    __device__ __forceinline__ void seed(uint64_t x, uint64_t, uint32_t, uint32_t, double *)
+    __device__ __forceinline__ void seed(uint64_t x, uint64_t, uint32_t, uint32_t, double *, int)
     {
         const uint64_t g = x ^ (x >> 1);
         sptr<uint32_t> c0 = aval(0, false);
@@ -638,11 +650,12 @@ __device__ __forceinline__ void group(Ops &S, const char *cols, uint32_t m)
 // One lane of item `it`: seed at xl, then the 2^c - 1 Gray steps of its
 // chunk (c = it.log2L).
 template <class Ops>
-__device__ __forceinline__ void walk_lane(Ops &S, const WaveItem &it, uint64_t xl, double *lds)
+__device__ __forceinline__ void walk_lane(Ops &S, const WaveItem &it, uint64_t xl,
+                                          double *lds_block, int stride)
 {
     const uint32_t c = it.log2L;
     const char *cols = S.cols;
-    S.seed(xl, it.x0, c, it.nlanes, lds);
+    S.seed(xl, it.x0, c, it.nlanes, lds_block, stride);
     if (c >= 3) {
         const uint32_t G = 1u << (c - 2);      // groups of four steps
         const uint32_t H = G >> 1;             // the group holding j = L/2
@@ -685,12 +698,13 @@ __device__ __forceinline__ double wave_sum(double v)
 
 template <class Ops>
 __device__ __forceinline__ void run_item(const WaveItem &it, const MatDesc &md, const char *stage,
-                                         double *partials, int lane, double *lds)
+                                         double *partials, int lane, double *lds_block,
+                                         int stride)
 {
     Ops S;
     S.setup(md, stage + md.stage_off);
     const uint64_t xl = it.x0 + ((uint64_t)lane << it.log2L);
-    walk_lane(S, it, xl, lds);
+    walk_lane(S, it, xl, lds_block, stride);
     double a, b;
     S.result(a, b);
     if ((uint32_t)lane >= it.nlanes) { a = 0.0; b = 0.0; }
@@ -986,7 +1000,6 @@ void walk_kernel(const WaveItem *items, uint32_t count, uint32_t grab,
     stage_in_walk(ca, mats, stage);
     stage = opaque(stage);              // no column load moves above the staging
     BlockClaims bc = block_claims(ctr, ca, slot);
-    double *lds = seed_lds + bc.wave * SL;
     const uint32_t per_run = WPB * grab;
     for_each_run(bc, lane, [&](uint32_t r) __attribute__((always_inline)) {
         r = __builtin_amdgcn_readfirstlane(r);
@@ -994,7 +1007,7 @@ void walk_kernel(const WaveItem *items, uint32_t count, uint32_t grab,
         for (uint32_t idx = r * per_run + bc.wave; idx < end; idx += WPB) {
             const WaveItem it = sload(items + idx);
             const MatDesc md = sload(mats + it.mat);
-            run_item<Ops>(it, md, stage, partials, lane, lds);
+            run_item<Ops>(it, md, stage, partials, lane, seed_lds, SL);
         }
     });
     finalize_in_walk(ca, mats, partials);
@@ -1004,20 +1017,23 @@ void walk_kernel(const WaveItem *items, uint32_t count, uint32_t grab,
 template <int N, bool KAHAN>
 __device__ __forceinline__ void run_variant(int v, const WaveItem &it, const MatDesc &md,
                                             const char *stage, double *partials, int lane,
-                                            double *lds)
+                                            double *lds_block, int stride)
 {
-    if (v == V_C128) run_item<OpsC128<N, KAHAN>>(it, md, stage, partials, lane, lds);
+    if (v == V_C128) run_item<OpsC128<N, KAHAN>>(it, md, stage, partials, lane, lds_block, stride);
     else if (v == V_F64)    // at the fused kernel's 3 waves f64 has registers for the prefetch
-        run_item<OpsF64<N, KAHAN, (N < PF_MAX ? N : PF_MAX)>>(it, md, stage, partials, lane, lds);
-    else run_item<OpsModp<N>>(it, md, stage, partials, lane, lds);
+        run_item<OpsF64<N, KAHAN, (N < PF_MAX ? N : PF_MAX)>>(it, md, stage, partials, lane,
+                                                              lds_block, stride);
+    else run_item<OpsModp<N>>(it, md, stage, partials, lane, lds_block, stride);
 }
 
 template <bool KAHAN, int... Ns>
 __device__ __forceinline__ void run_fused(std::integer_sequence<int, Ns...>, int n, int v,
                                           const WaveItem &it, const MatDesc &md, const char *stage,
-                                          double *partials, int lane, double *lds)
+                                          double *partials, int lane, double *lds_block,
+                                          int stride)
 {
-    (void)((n == Ns + 1 ? (run_variant<Ns + 1, KAHAN>(v, it, md, stage, partials, lane, lds), true)
+    (void)((n == Ns + 1 ? (run_variant<Ns + 1, KAHAN>(v, it, md, stage, partials, lane, lds_block,
+                                                      stride), true)
                         : false) || ...);
 }
 
@@ -1037,7 +1053,6 @@ void walk_fused(const WaveItem *items, uint32_t count, uint32_t grab,
     stage_in_walk(ca, mats, stage);
     stage = opaque(stage);              // no column load moves above the staging
     BlockClaims bc = block_claims(ctr, ca, slot);
-    double *lds = seed_lds + bc.wave * SL;
     const uint32_t per_run = WPB * grab;
     for_each_run(bc, lane, [&](uint32_t r) __attribute__((always_inline)) {
         r = __builtin_amdgcn_readfirstlane(r);
@@ -1046,7 +1061,7 @@ void walk_fused(const WaveItem *items, uint32_t count, uint32_t grab,
             const WaveItem it = sload(items + idx);
             const MatDesc md = sload(mats + it.mat);
             run_fused<KAHAN>(std::make_integer_sequence<int, NF>{}, md.n, md.variant, it, md,
-                             stage, partials, lane, lds);
+                             stage, partials, lane, seed_lds, SL);
         }
     });
     finalize_in_walk(ca, mats, partials);
