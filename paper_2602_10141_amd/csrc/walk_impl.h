@@ -703,7 +703,11 @@ __device__ __forceinline__ void run_item(const WaveItem &it, const MatDesc &md, 
 {
     Ops S;
     S.setup(md, stage + md.stage_off);
-    const uint64_t xl = it.x0 + ((uint64_t)lane << it.log2L);
+    // the lane's start index, its 64-bit lane offset formed afresh per item
+    // (kept across the item loop, it was spilled there)
+    int ln = lane;
+    asm volatile("" : "+v"(ln));
+    const uint64_t xl = it.x0 + ((uint64_t)(uint32_t)ln << it.log2L);
     walk_lane(S, it, xl, lds_block, stride);
     double a, b;
     S.result(a, b);
