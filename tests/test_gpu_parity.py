@@ -289,7 +289,8 @@ def test_batch_mixed_matches_single_bitwise(P, ctx, O):
 
 
 @pytest.mark.parametrize("field,n", [("c128", 16), ("c128", 20), ("c128", 22), ("c128", 24),
-                                     ("c128", 26), ("f64", 20), ("f64", 24), ("f64", 27),
+                                     ("c128", 26), ("f64", 20), ("f64", 24), ("f64", 26),
+                                     ("f64", 27),
                                      ("modp", 20), ("modp", 24)])
 def test_latency_partition_single_calls(P, ctx, O, field, n):
     """One matrix of order 16..27 alone would leave most resident waves idle
@@ -353,6 +354,26 @@ def test_block_claims_small_grids(P, ctx, O, count):
         assert v == P.perm_c128(ctx, A, flags=P.PERM_SHARED_PARTITION)
         assert abs(P.perm_c128(ctx, A) - v) <= TOL * scale(A)
         assert abs(v - O.native.ryser_c128(A)) <= TOL * scale(A)
+
+
+def test_block_staging_small_batches(P, ctx, O):
+    """A batch whose one walk is short and covers at most four small
+    matrices stages them in every block of the walk instead of in a launch of
+    its own.  Its results equal those of the same matrices inside a batch
+    that takes the stage launch, bit for bit, and the oracle."""
+    p = 1073742209
+    g = E.rng(16, 0)
+    small = [(E.ginibre_complex(19, g), "c128", 0), (E.ginibre_real(20, g), "f64", 0),
+             (E.random_residues(18, p, g), "modp", p)]
+    big = small + [(E.ginibre_complex(12, g), "c128", 0) for _ in range(30)]
+    items, data = P.pack_matrices(small)
+    vals = P.batch_values(items, P.perm_batch(ctx, items, data))
+    items_b, data_b = P.pack_matrices(big)
+    vals_b = P.batch_values(items_b, P.perm_batch(ctx, items_b, data_b))
+    assert vals == vals_b[:3]
+    assert abs(vals[0] - O.native.ryser_c128(small[0][0])) <= TOL * scale(small[0][0])
+    assert abs(vals[1] - O.native.ryser_f64(small[1][0])) <= TOL * scale(small[1][0])
+    assert vals[2] == O.native.ryser_modp(small[2][0], p)
 
 
 def test_multi_item_claims_tiny_matrices(P, ctx, O):
