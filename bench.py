@@ -939,13 +939,18 @@ def sub_sizes(P, ctx, args):
         reps = max(1, int(4e9 / terms))
         fn()
         sync()
-        P.perm_prof_enable(ctx, True)
-        P.perm_prof_read(ctx)
+        # call time without timing events (they add about 9 us to a call),
+        # walk time from a second, profiled pass
         t0 = time.perf_counter()
         for _ in range(reps):
             fn()
         sync()
         dt = (time.perf_counter() - t0) / reps
+        P.perm_prof_enable(ctx, True)
+        P.perm_prof_read(ctx)
+        for _ in range(max(1, reps // 4)):
+            fn()
+        sync()
         walk_ms, launches = P.perm_prof_read(ctx)
         P.perm_prof_enable(ctx, False)
         ops = terms * ops_per_term(field, n)
