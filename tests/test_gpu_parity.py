@@ -164,7 +164,7 @@ def test_schur_modp(P, ctx, O, n):
             assert want == 0
 
 
-@pytest.mark.parametrize("n", [5, 7, 9, 11, 13])
+@pytest.mark.parametrize("n", [5, 7, 9, 11, 13, 17, 19])
 def test_schur_crt_exact(P, ctx, O, n):
     primes = P.perm_schur_primes(n)
     assert primes == O.crt.primes_for_schur(n)
