@@ -588,7 +588,13 @@ struct OpsMont {
 
 template <int V, int N, bool K> struct OpsFor;
 template <int N, bool K> struct OpsFor<V_C128, N, K> { using type = OpsC128<N, K>; };
-template <int N, bool K> struct OpsFor<V_F64, N, K> { using type = OpsF64<N, K>; };
+// f64 prefetches the whole column at orders 16..28 (at four waves per SIMD,
+// below), elsewhere none (see Occupancy).
+template <int N>
+struct PfF64 {
+    static constexpr int n = (N >= 16 && N <= 28) ? N : 0;
+};
+template <int N, bool K> struct OpsFor<V_F64, N, K> { using type = OpsF64<N, K, PfF64<N>::n>; };
 template <int N, bool K> struct OpsFor<V_MODP, N, K> { using type = OpsModp<N>; };
 template <int N, bool K> struct OpsFor<V_MONT, N, K> { using type = OpsMont<N>; };
 
@@ -736,15 +742,19 @@ __device__ __forceinline__ uint32_t next_item(unsigned long long *ctr, uint64_t 
 // waves for n = 20..28; F_p (Barrett) runs at 3 waves from n = 21 up to 48
 // (the walk loop stays free of spills; from n = 36 the per-item seed
 // spills, once per item) and F_p (Montgomery) at 4 compiles without spills;
-// both run as fast as any setting measured; f64 gains more from occupancy
-// (7 waves at n = 20) than it loses to a few spilled registers.
+// both run as fast as any setting measured.  f64 at orders 16..28 runs at 4
+// waves with the whole column prefetched (as in the fused kernel), which
+// keeps its walk loop free of spills: against 5..8 waves without prefetch a
+// batch of 50,000 O(20) walked 3% faster and single calls 9-17%; batches
+// of orders 10..13 were 3-9% slower that way and keep the occupancy, as do
+// orders from 29 (2% slower at 32).
 template <int V, int N>
 struct Occupancy {
     static constexpr int clamp(int w) { return w < 1 ? 1 : (w > 8 ? 8 : w); }
     static constexpr int waves =
         V == V_C128 ? clamp(512 / (4 * N + 56))
       : V == V_MODP ? (N > 20 ? 3 : N > 12 ? 4 : clamp(512 / (2 * N + 44)))
-      : V == V_F64  ? clamp(512 / (2 * N + 32))
+      : V == V_F64  ? (N >= 16 && N <= 28 ? 4 : clamp(512 / (2 * N + 32)))
                     : (N > 40 ? 3 : 4);
 };
 
