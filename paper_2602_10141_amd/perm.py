@@ -127,8 +127,19 @@ def _is_dev(x):
     return isinstance(x, torch.Tensor) and x.is_cuda
 
 
-def _stream(stream):
+# The current stream's raw handle without building a torch.cuda.Stream
+# object (about 3 us per call, a fifth of a small permanent's call time).
+_current_raw_stream = getattr(torch._C, "_cuda_getCurrentRawStream", None)
+
+
+def _stream(stream, device=None):
+    """A hipStream_t for the library: `stream` (torch.cuda.Stream or a raw
+    handle), or torch's current stream on `device` (default: the current
+    device) when it is None."""
     if stream is None:
+        if _current_raw_stream is not None:
+            dev = torch.cuda.current_device() if device is None else device
+            return ctypes.c_void_p(_current_raw_stream(dev))
         return ctypes.c_void_p(torch.cuda.current_stream().cuda_stream)
     if isinstance(stream, torch.cuda.Stream):
         return ctypes.c_void_p(stream.cuda_stream)
@@ -184,7 +195,8 @@ def _single(fn, ctx, A, n_out, dtype_out, extra, flags, stream):
             raise ValueError("expected a contiguous square CUDA tensor")
         out = torch.empty(n_out, dtype=dtype_out, device=A.device)
         _check(fn(ctx.ptr, ctypes.c_void_p(A.data_ptr()), A.shape[0], *extra,
-                  ctypes.c_void_p(out.data_ptr()), flags | PERM_DEVICE_PTRS, _stream(stream)))
+                  ctypes.c_void_p(out.data_ptr()), flags | PERM_DEVICE_PTRS,
+                  _stream(stream, A.device.index)))
         return out
     return None
 
@@ -216,7 +228,7 @@ def perm_c128_noalloc(ctx, A, out=None, flags=0, stream=None):
         out = torch.empty(2, dtype=torch.float64, device=A.device)
     _check(lib().perm_c128_noalloc(ctx.ptr, ctypes.c_void_p(A.data_ptr()), A.shape[0],
                                    ctypes.c_void_p(out.data_ptr()), flags | PERM_DEVICE_PTRS,
-                                   _stream(stream)))
+                                   _stream(stream, A.device.index)))
     return out
 
 
@@ -266,7 +278,7 @@ def perm_crt_int(ctx, mats, primes, log2_bound: float, flags=0, stream=None):
             raise TypeError("device matrices must be a contiguous int32 tensor (k, n, n)")
         n = mats.shape[-1]
         ptr, fl = ctypes.c_void_p(mats.data_ptr()), flags | PERM_DEVICE_PTRS
-        st = _stream(stream)
+        st = _stream(stream, mats.device.index)
     else:
         m = np.ascontiguousarray(mats, dtype=np.uint32)
         n = m.shape[-1]
@@ -360,7 +372,7 @@ def perm_batch(ctx, items, data, out=None, flags=0, stream=None):
             out = torch.zeros((max(count, 1), 2), dtype=torch.float64, device=data.device)
         rc = lib().perm_batch(ctx.ptr, items.ctypes.data, count, ctypes.c_void_p(data.data_ptr()),
                               ctypes.c_void_p(out.data_ptr()), ctypes.byref(bad),
-                              flags | PERM_DEVICE_PTRS, _stream(stream))
+                              flags | PERM_DEVICE_PTRS, _stream(stream, data.device.index))
     else:
         d = np.ascontiguousarray(data)
         out = np.zeros((max(count, 1), 2), dtype=np.float64)
