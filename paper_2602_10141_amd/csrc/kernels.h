@@ -114,8 +114,13 @@ int launch_stage(const MatDesc *d_mats, int nmats, const void *src, void *stage,
 constexpr int CTR_GROUPS = 8;
 constexpr int CTR_STRIDE = 32;                                  // in uint64
 constexpr size_t CTR_BYTES = (size_t)CTR_GROUPS * CTR_STRIDE * 8;
+// The blocks of a launch that finalizes in its last block count themselves
+// done on the uint64 at this index (in counter group 0's 256 bytes, a cache
+// line away from its claim counter).
+constexpr int CTR_DONE = 16;
 struct CtrState {
     uint64_t base[CTR_GROUPS] = {};
+    uint64_t done = 0;
 };
 inline uint32_t ctr_groups(int grid_blocks)
 {
@@ -129,8 +134,9 @@ struct CtrArgs {                 // kernel argument (by value)
     uint32_t runs;               // runs of items, computed on the host
     char *fin_out;               // fin_nmats > 0: every block stages matrices
     const char *fin_src;         //   0 .. fin_nmats from fin_src before walking;
-    uint32_t fin_nmats;          //   a one-block launch with fin_out also
-    uint32_t pad;                //   finalizes them into fin_out
+    uint32_t fin_nmats;          //   with fin_out the last block to finish
+    uint32_t pad;                //   also finalizes them into fin_out
+    uint64_t done_base;          // the done counter's value before the launch
 };
 
 // Items are walked in runs of (BLOCK / WAVE) * grab consecutive items
@@ -141,9 +147,11 @@ struct CtrArgs {                 // kernel argument (by value)
 // is advanced past it.  With fin_nmats > 0 (the call's matrices being all of
 // d_mats[0 .. fin_nmats)) every block first does launch_stage's work from
 // fin_src, and the caller does not launch it: the blocks write the same bytes
-// and each reads only after its own barrier.  With fin_out as well (only for
-// grid_blocks == 1) the block also does launch_finalize's work into fin_out
-// last, and the caller does not launch that either.
+// and each reads only after its own stores and barrier.  With fin_out as
+// well the block that finishes last (the only one, for grid_blocks == 1)
+// also does launch_finalize's work into fin_out, and the caller does not
+// launch that either; with several blocks they count themselves done on
+// ctr[CTR_DONE], whose value the host tracks in state->done.
 int launch_walk(int variant, int n, bool kahan, bool fused, int nmax_fused,
                 const WaveItem *d_items, uint32_t count, uint32_t grab, const MatDesc *d_mats,
                 const void *stage, double *partials, unsigned long long *ctr,

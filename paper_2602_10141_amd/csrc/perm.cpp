@@ -215,18 +215,21 @@ static int occupancy_of(perm_ctx *ctx, int variant, int n, bool kahan)
 // The latency partition.  The default chunk length of (variant, n) is set
 // for batches that fill the device; a call with only `nmats` whole matrices
 // of that kind may leave most resident waves idle (one c128 matrix of order
-// 24 is 128 items on 3,072 resident waves).  Its time is about
-//   ceil(items / slots) x (2^c x step cost + seed cost + item cost)
-// per lane; the chunk length minimising it (down to 2^4) is used, the
-// default when that fills the device already.  Below order 16 a whole call
-// is a few microseconds of walk in one block, which the two extra launches
-// of a multi-block call would outweigh, so the default stays.  Only F_p
-// results (exact) and single float calls without PERM_SHARED_PARTITION take
-// it: the summation order of a float result follows the partition.
+// 24 is 128 items on 3,072 resident waves, one of order 14 a single block
+// of four waves walking 2^5 indices a lane).  Its time is about
+//   ceil(items / slots) x 2^c x step cost + ceil(items / SIMDs) x item cost
+// in instruction slots of one SIMD: the walks of a round of `slots` waves
+// share the SIMDs' issue, while each wave a SIMD holds adds its seed and
+// item overhead (the seeds' loads of the matrix contend for the CU's caches
+// and the extra blocks stage the matrix again).  The chunk length minimising
+// it (down to 2^3, the shortest the unrolled walk takes) is used, the
+// default when that fills the device already.  Only F_p results (exact) and
+// single float calls without PERM_SHARED_PARTITION take it: the summation
+// order of a float result follows the partition.
 int latency_log2_chunk(const perm_ctx *ctx, int variant, int n, uint64_t nmats, int blocks_per_cu)
 {
     const int c0 = log2_chunk_for(ctx, variant, n);
-    if (n < 16) return c0;
+    if (n < 10) return c0;        // one item of at most 2^3 indices a lane holds it all
     const int field = variant == V_MONT ? PERM_MODP : variant;
     auto it = ctx->tune.find({field, n});
     if (it != ctx->tune.end() && it->second.log2_chunk > 0) return c0;   // the table decides
@@ -241,19 +244,25 @@ int latency_log2_chunk(const perm_ctx *ctx, int variant, int n, uint64_t nmats, 
     const uint64_t T = 1ull << (n - 1);
     auto items = [&](int c) { return nmats * (T >= (64ull << c) ? T >> (6 + c) : 1ull); };
     if (items(c0) >= slots) return c0;
-    // seed: the wave's common part (about n instructions a lane) and the
-    // seven columns whose signs differ across its lanes, each an update of
-    // the n row sums (two words each for c128; the Montgomery walk updates
-    // for all n - 1 columns); per item about 64 more (claim, descriptor
-    // loads, LDS exchange, wave sum)
+    // item cost: the seed's instructions -- the wave's common part (about n
+    // a lane) and the seven columns whose signs differ across its lanes,
+    // each an update of the n row sums (two words each for c128; the
+    // Montgomery walk updates for all n - 1 columns) -- and about 1,860 slots
+    // of latency and overhead (claim, loads of the descriptors and the
+    // matrix, LDS exchange, wave sum), fitted to single calls of orders
+    // 10..23 timed at every chunk length: 2^3 fastest up to order 20, then
+    // one wave per SIMD (2^4 at 21, 2^5 at 22) rather than two of half the
+    // length
     const int upd = variant == V_MONT ? n - 1 : std::min(n - 1, 7);
-    const double seed = (double)upd * n * (variant == V_C128 ? 2.0 : 1.0) + n + 64.0;
+    const double item = (double)upd * n * (variant == V_C128 ? 2.0 : 1.0) + n + 1860.0;
     const double step = (double)step_cost(variant, n);
+    const double simds = (double)ctx->num_cus * (BLOCK / WAVE);
     int best = c0;
     double best_t = 1e300;
-    for (int c = c0; c >= 4; --c) {
+    for (int c = c0; c >= 3; --c) {
         const double rounds = std::ceil((double)items(c) / (double)slots);
-        const double t = rounds * (std::ldexp(1.0, c) * step + seed);
+        const double waves = std::ceil((double)items(c) / simds);
+        const double t = rounds * std::ldexp(1.0, c) * step + waves * item;
         if (t < 0.98 * best_t) {          // a shorter chunk only when clearly faster
             best_t = t;
             best = c;
@@ -261,6 +270,12 @@ int latency_log2_chunk(const perm_ctx *ctx, int variant, int n, uint64_t nmats, 
     }
     return best;
 }
+
+// A call that is one short walk launch of at most this many blocks
+// finalizes in its last block instead of in a launch of its own (with more,
+// the blocks' device-scope releases cost more than that launch: one U(19)
+// in 64 blocks took 0.9 us longer per call).
+constexpr int kFinInWalkMaxGrid = 32;
 
 // Plans of at most this many matrices are cached (repeated small calls such
 // as a CRT over a few primes); larger ones cost more to compare than to build.
@@ -598,16 +613,18 @@ int execute(perm_ctx *ctx, Plan &pl, const void *src, void *out, size_t out_slot
     // in every block instead of in a launch of its own: such calls are
     // bound by the host's launches, which cost more than the blocks' copies
     // of at most 16 entries per thread cost the device (one U(16)..U(20) or
-    // O(20) per call 11-14% faster).
-    const bool one_block = walks == 1 && shape[last].grid == 1;
+    // O(20) per call 11-14% faster).  With at most kFinInWalkMaxGrid blocks
+    // the last block to finish also finalizes (one launch per call).
     size_t entries = 0;
     uint64_t terms = 0;
     for (const MatDesc &d : pl.mats) {
         entries += (size_t)d.n * d.n;
         terms += d.n > 0 ? 1ull << (d.n - 1) : 0;
     }
-    const bool block_stage = one_block || (walks == 1 && pl.mats.size() <= 4 &&
-                                           entries <= 16 * BLOCK && terms <= (1ull << 26));
+    const bool block_stage = walks == 1 && (shape[last].grid == 1 ||
+                                            (pl.mats.size() <= 4 && entries <= 16 * BLOCK &&
+                                             terms <= (1ull << 26)));
+    const bool fin_in_walk = block_stage && shape[last].grid <= kFinInWalkMaxGrid;
     if (!block_stage)
         HIPCHK((hipError_t)launch_stage(d_mats, (int)pl.mats.size(), src, ctx->stage.p, s));
     for (size_t q = 0; q < pl.groups.size(); ++q) {
@@ -637,7 +654,7 @@ int execute(perm_ctx *ctx, Plan &pl, const void *src, void *out, size_t out_slot
                                        ctx->stage.p, (double *)ctx->partials.p,
                                        (unsigned long long *)ctx->ctr.p, &ctx->ctr_state,
                                        shape[q].grid, s, block_stage ? src : nullptr,
-                                       one_block ? out : nullptr,
+                                       fin_in_walk ? out : nullptr,
                                        block_stage ? (int)pl.mats.size() : 0));
         if (prof) {
             HIPCHK(hipEventRecord(ev.second, s));
@@ -645,7 +662,7 @@ int execute(perm_ctx *ctx, Plan &pl, const void *src, void *out, size_t out_slot
             ctx->prof_pending.push_back(ev);
         }
     }
-    if (!one_block)
+    if (!fin_in_walk)
         HIPCHK((hipError_t)launch_finalize(d_mats, (int)pl.mats.size(),
                                            (const double *)ctx->partials.p, out, s));
     return PERM_OK;
@@ -887,7 +904,7 @@ extern "C" int perm_c128_noalloc(perm_ctx *ctx, const double *A, int n, double *
         const uint32_t grab = std::max(1u, std::min(grab_for(log2L), cnt / (2 * resident)));
         const uint32_t runs = (cnt + grab * (BLOCK / WAVE) - 1) / (grab * (BLOCK / WAVE));
         const int grid = (int)std::max(1u, std::min(runs, (uint32_t)(per_cu * ctx->num_cus)));
-        const bool one_block = grid == 1;
+        const bool fin_in_walk = grid <= kFinInWalkMaxGrid;
         const MatDesc *d_mats = (const MatDesc *)(base + L.mat);
         void *stage = base + L.stage;
         double *partials = (double *)(base + L.partials);
@@ -896,8 +913,8 @@ extern "C" int perm_c128_noalloc(perm_ctx *ctx, const double *A, int n, double *
         HIPCHK((hipError_t)launch_walk(V_C128, n, kahan, false, 0,
                                        (const WaveItem *)(base + L.items), cnt, grab, d_mats, stage,
                                        partials, (unsigned long long *)(base + L.ctr), &st, grid, s,
-                                       A, one_block ? out : nullptr, 1));
-        if (!one_block) HIPCHK((hipError_t)launch_finalize(d_mats, 1, partials, out, s));
+                                       A, fin_in_walk ? out : nullptr, 1));
+        if (!fin_in_walk) HIPCHK((hipError_t)launch_finalize(d_mats, 1, partials, out, s));
     }
     return end_call(ctx, s);
 }

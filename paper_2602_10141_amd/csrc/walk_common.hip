@@ -67,7 +67,7 @@ int launch_walk(int variant, int n, bool kahan, bool fused, int nmax_fused, cons
     WalkFn f = pick(variant, n, kahan, fused, nmax_fused);
     if (!f || grab < 1 || !state) return (int)hipErrorInvalidValue;
     if (grid_blocks < 1) grid_blocks = 1;
-    if (fin_nmats < 0 || (fin_nmats > 0 && !fin_src) || (fin_out && (grid_blocks != 1 || !fin_nmats)))
+    if (fin_nmats < 0 || (fin_nmats > 0 && !fin_src) || (fin_out && !fin_nmats))
         return (int)hipErrorInvalidValue;
     const uint64_t per_run = (uint64_t)(BLOCK / WAVE) * grab;
     const uint64_t runs = ((uint64_t)count + per_run - 1) / per_run;
@@ -77,6 +77,7 @@ int launch_walk(int variant, int n, bool kahan, bool fused, int nmax_fused, cons
     ca.fin_out = (char *)fin_out;
     ca.fin_src = (const char *)fin_src;
     ca.fin_nmats = (uint32_t)fin_nmats;
+    ca.done_base = state->done;
     for (int x = 0; x < CTR_GROUPS; ++x) ca.base[x] = state->base[x];
     const char *st = (const char *)stage;
     void *args[] = {(void *)&d_items, (void *)&count, (void *)&grab, (void *)&d_mats, (void *)&st,
@@ -90,6 +91,7 @@ int launch_walk(int variant, int n, bool kahan, bool fused, int nmax_fused, cons
     const uint64_t g = ca.groups;
     if (runs > (uint64_t)grid_blocks)
         for (uint64_t x = 0; x < g; ++x) state->base[x] += runs > x ? (runs - x + g - 1) / g : 0;
+    if (fin_out && grid_blocks > 1) state->done += (uint64_t)grid_blocks;
     return (int)hipGetLastError();
 }
 

@@ -966,30 +966,61 @@ __device__ __forceinline__ void for_each_run(BlockClaims &bc, int lane, F &&walk
     for (uint32_t r = blockIdx.x; r < bc.runs; r = claims ? bc.next(lane) : bc.runs) walk_run(r);
 }
 
+// Wait until this wave's vector stores are written to L2.  The workgroup
+// barrier does not (it waits for LDS and scalar operations only), which is
+// enough for the vector loads of other waves of the CU, but not for scalar
+// loads, which reach L2 through the scalar cache.
+__device__ __forceinline__ void wait_stores()
+{
+    asm volatile("s_waitcnt vmcnt(0)" ::: "memory");
+}
+
 // A launch over a few small matrices stages them in every block before
-// walking, saving the stage launch; one that is the whole call in one block
-// (a single small matrix, or a few tiny ones) also finalizes them afterwards,
-// saving the finalize launch.  The blocks write the same bytes.  A block's
-// vector stores complete before its barrier, and its waves read the staged
-// lines only after that barrier, from this XCD's L2, which then holds the
-// block's own write or another block's identical one; the scalar and vector
-// L1 caches start every dispatch empty, so a line they hold was fetched
-// after some block of the XCD had written it.
+// walking, saving the stage launch; one that is the whole call (a single
+// small matrix, or a few tiny ones) also finalizes them afterwards, in the
+// block that finishes last, saving the finalize launch.  The blocks write
+// the same bytes.  Every wave's stores reach L2 before the block's barrier,
+// and its waves read the staged columns only after that barrier, from this
+// XCD's L2, which then holds the block's own write or another block's
+// identical one; the scalar and vector L1 caches start every dispatch
+// empty, so a line they hold was fetched after some block of the XCD had
+// written it.
 __device__ __forceinline__ void stage_in_walk(const CtrArgs &ca, const MatDesc *mats,
                                               const char *stage)
 {
     if (!ca.fin_nmats) return;
     for (uint32_t m = 0; m < ca.fin_nmats; ++m)
         stage_one(mats[m], ca.fin_src, const_cast<char *>(stage));
+    wait_stores();
     __syncthreads();
 }
 
+// With several blocks, each counts itself done on ctr[CTR_DONE] once its
+// waves' partials are in L2: wave 0 releases at device scope (writing the
+// XCD's L2 back to memory) in the atomic, and the block that takes the last
+// count acquires (dropping its stale L1 and L2 lines) before it reads the
+// other blocks' partials.  One release per block: a device-scope fence in
+// every wave, after each item, cost more than the finalize launch it saved.
 __device__ __forceinline__ void finalize_in_walk(const CtrArgs &ca, const MatDesc *mats,
-                                                 const double *partials)
+                                                 const double *partials,
+                                                 unsigned long long *ctr)
 {
     if (!ca.fin_nmats || !ca.fin_out) return;
     __shared__ double sa[256], sb[256];
     __shared__ unsigned long long su[256];
+    if (gridDim.x > 1) {
+        __shared__ uint32_t last;
+        wait_stores();
+        __syncthreads();
+        if (threadIdx.x == 0) {
+            const unsigned long long before = __hip_atomic_fetch_add(
+                ctr + CTR_DONE, 1ull, __ATOMIC_RELEASE, __HIP_MEMORY_SCOPE_AGENT);
+            last = before - ca.done_base == gridDim.x - 1u;
+        }
+        __syncthreads();
+        if (!last) return;
+        __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "agent");
+    }
     for (uint32_t m = 0; m < ca.fin_nmats; ++m) {
         __syncthreads();
         finalize_one(mats[m], partials, ca.fin_out, sa, sb, su);
@@ -1024,7 +1055,7 @@ void walk_kernel(const WaveItem *items, uint32_t count, uint32_t grab,
             run_item<Ops>(it, md, stage, partials, lane, seed_lds, SL);
         }
     });
-    finalize_in_walk(ca, mats, partials);
+    finalize_in_walk(ca, mats, partials, ctr);
 }
 
 // Fused kernel: any mix of c128 / f64 / F_p (Barrett) matrices of order <= NF.
@@ -1078,7 +1109,7 @@ void walk_fused(const WaveItem *items, uint32_t count, uint32_t grab,
                              stage, partials, lane, seed_lds, SL);
         }
     });
-    finalize_in_walk(ca, mats, partials);
+    finalize_in_walk(ca, mats, partials, ctr);
 }
 
 // ------------------------------------------------ instantiation tables

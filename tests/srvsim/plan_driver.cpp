@@ -156,10 +156,11 @@ static void check_tune_files(perm_ctx *ctx)
 }
 
 // The latency partition: a lone matrix whose batch partition leaves
-// resident waves idle is split finer (never below 2^4 indices per lane, and
-// never for orders below 16); the batch partition stays for calls that fill
-// the device, for matrices not marked latency-eligible, and for (field, n)
-// with a tuning-table entry.  Either way the range is tiled exactly once.
+// resident waves idle is split finer (never below 2^3 indices per lane, and
+// never for orders below 10, where one item holds the whole range); the
+// batch partition stays for calls that fill the device, for matrices not
+// marked latency-eligible, and for (field, n) with a tuning-table entry.
+// Either way the range is tiled exactly once.
 static void check_latency_partition(perm_ctx *ctx)
 {
     ctx->tune.clear();
@@ -169,7 +170,7 @@ static void check_latency_partition(perm_ctx *ctx)
     auto slots_of = [](int variant) { return (variant == V_F64 ? 3ull : 2ull) * 256 * 4; };
     Plan pl;
     for (int variant : {(int)V_C128, (int)V_F64, (int)V_MODP})
-        for (int n = 12; n <= 32; ++n) {
+        for (int n = 8; n <= 32; ++n) {
             const uint64_t slots = slots_of(variant);
             std::vector<MatIn> in(1);
             in[0].variant = variant;
@@ -185,11 +186,15 @@ static void check_latency_partition(perm_ctx *ctx)
             check_plan(ctx, in, pl);
             const uint32_t items = (uint32_t)pl.items.size();
             const uint32_t c0 = pl.items[0].log2L;
-            if (n < 16 || items >= slots) {
+            if (n < 10 || items >= slots) {
                 CHECK(lat_items == items, "v%d n=%d: latency partition where the batch one fills", variant, n);
             } else {
-                CHECK(lat_c <= c0 && (lat_c >= 4 || lat_c == c0), "v%d n=%d: chunk 2^%u", variant, n, lat_c);
+                CHECK(lat_c <= c0 && (lat_c >= 3 || lat_c == c0), "v%d n=%d: chunk 2^%u", variant, n, lat_c);
                 CHECK(lat_items >= items, "v%d n=%d: fewer items", variant, n);
+                // a lone matrix that one wave per SIMD holds at 2^3
+                // indices per lane takes that length
+                if ((1ull << (n - 1)) >> 9 <= 256ull * 4)
+                    CHECK(lat_c == 3, "v%d n=%d: chunk 2^%u, not 2^3", variant, n, lat_c);
             }
             // a table entry decides
             perm_tune t{c0 > 4 ? (int)c0 - 1 : (int)c0, 0};

@@ -288,12 +288,13 @@ def test_batch_mixed_matches_single_bitwise(P, ctx, O):
                 assert v == (O.native.ryser_modp(A, p) if n else 1)
 
 
-@pytest.mark.parametrize("field,n", [("c128", 16), ("c128", 20), ("c128", 22), ("c128", 24),
-                                     ("c128", 26), ("f64", 20), ("f64", 24), ("f64", 26),
-                                     ("f64", 27),
-                                     ("modp", 20), ("modp", 24)])
+@pytest.mark.parametrize("field,n", [("c128", 11), ("c128", 14), ("c128", 15), ("c128", 16),
+                                     ("c128", 20), ("c128", 22), ("c128", 24),
+                                     ("c128", 26), ("f64", 13), ("f64", 17), ("f64", 20),
+                                     ("f64", 24), ("f64", 26), ("f64", 27),
+                                     ("modp", 14), ("modp", 20), ("modp", 24)])
 def test_latency_partition_single_calls(P, ctx, O, field, n):
-    """One matrix of order 16..27 alone would leave most resident waves idle
+    """One matrix of order 10..27 alone would leave most resident waves idle
     at the batch partition, so a single call splits it into more, shorter
     wave items.  The result agrees with the oracle (orders up to 24) and
     with the same matrix in a batch to within the tolerance (bit for bit for
@@ -374,6 +375,64 @@ def test_block_staging_small_batches(P, ctx, O):
     assert abs(vals[0] - O.native.ryser_c128(small[0][0])) <= TOL * scale(small[0][0])
     assert abs(vals[1] - O.native.ryser_f64(small[1][0])) <= TOL * scale(small[1][0])
     assert vals[2] == O.native.ryser_modp(small[2][0], p)
+
+
+def test_last_block_finalize_back_to_back(P, ctx, O):
+    """A single call of order 11..17 walks in 1 to 32 blocks and finalizes in
+    the block that finishes last, counted on a device counter whose value
+    the host tracks across calls.  Many such calls of different matrices,
+    orders and fields, queued without synchronising and mixed with batches
+    and CRT calls that finalize in a launch of their own or in one block,
+    each give the bits of the same call made alone, and the oracle's
+    result."""
+    import torch
+    p = 1073742209
+    g = E.rng(17, 0)
+    cases = []
+    for rep in range(3):
+        for n in (11, 12, 13, 14, 15, 16, 17):
+            cases.append(("c128", E.ginibre_complex(n, g)))
+            cases.append(("f64", E.ginibre_real(n, g)))
+            cases.append(("modp", E.random_residues(n, p, g)))
+    alone = []
+    for field, A in cases:
+        if field == "c128":
+            alone.append(P.perm_c128(ctx, A))
+        elif field == "f64":
+            alone.append(P.perm_f64(ctx, A))
+        else:
+            alone.append(P.perm_modp(ctx, A, p))
+    dev = [torch.from_numpy(A.astype(np.int32) if f == "modp" else A).cuda() for f, A in cases]
+    batch = [(E.ginibre_complex(12, g), "c128", 0) for _ in range(40)]
+    items, data = P.pack_matrices(batch)
+    torch.cuda.synchronize()
+    outs = []
+    for i, ((field, A), d) in enumerate(zip(cases, dev)):
+        if field == "c128":
+            outs.append(P.perm_c128(ctx, d))
+        elif field == "f64":
+            outs.append(P.perm_f64(ctx, d))
+        else:
+            outs.append(P.perm_modp(ctx, d, p))
+        if i % 10 == 0:
+            P.perm_batch(ctx, items, data)
+        if i % 25 == 0:             # 3 primes x 2^12 indices: every block stages and finalizes
+            m = 13
+            J = np.stack([np.ones((m, m), np.uint32)] * 3)
+            val, _ = P.perm_crt_int(ctx, J, O.crt.primes_1_mod_n(2, 3),
+                                    math.log2(math.factorial(m)) + 1)
+            assert val == math.factorial(m)
+    torch.cuda.synchronize()
+    for (field, A), o, want in zip(cases, outs, alone):
+        o = o.cpu().numpy()
+        if field == "c128":
+            assert complex(o[0], o[1]) == want
+            assert abs(want - O.native.ryser_c128(A)) <= TOL * scale(A)
+        elif field == "f64":
+            assert o[0] == want
+            assert abs(want - O.native.ryser_f64(A)) <= TOL * scale(A)
+        else:
+            assert int(o[0]) == want == O.native.ryser_modp(A, p)
 
 
 def test_multi_item_claims_tiny_matrices(P, ctx, O):
