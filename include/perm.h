@@ -114,7 +114,7 @@ int perm_c128(perm_ctx *ctx, const double *A, int n, double *out, unsigned flags
  * A: device, n*n complex128 row-major, 8-byte aligned.  out: device, 2
  * doubles (re, im), 8-byte aligned.  flags must contain PERM_DEVICE_PTRS
  * (PERM_NO_KAHAN, PERM_SHARED_PARTITION allowed); asynchronous on `stream`
- * (NULL: the context's).
+ * (NULL: HIP's null stream).
  * 0 <= n <= 32.  Every call on a device shares that device's scratch: calls
  * that overlap on one device (different streams, contexts or threads) race;
  * calls on one stream are ordered.
