@@ -380,17 +380,18 @@ def test_block_staging_small_batches(P, ctx, O):
 def test_last_block_finalize_back_to_back(P, ctx, O):
     """A single call of order 11..17 walks in 1 to 32 blocks and finalizes in
     the block that finishes last, counted on a device counter whose value
-    the host tracks across calls.  Many such calls of different matrices,
-    orders and fields, queued without synchronising and mixed with batches
-    and CRT calls that finalize in a launch of their own or in one block,
-    each give the bits of the same call made alone, and the oracle's
+    the host tracks across calls; from order 18 (64 blocks and more) a
+    finalize launch follows the walk.  Many such calls of different
+    matrices, orders and fields, queued without synchronising and mixed with
+    batches and CRT calls that finalize in a launch of their own or in one
+    block, each give the bits of the same call made alone, and the oracle's
     result."""
     import torch
     p = 1073742209
     g = E.rng(17, 0)
     cases = []
     for rep in range(3):
-        for n in (11, 12, 13, 14, 15, 16, 17):
+        for n in (11, 12, 13, 14, 15, 16, 17, 18):
             cases.append(("c128", E.ginibre_complex(n, g)))
             cases.append(("f64", E.ginibre_real(n, g)))
             cases.append(("modp", E.random_residues(n, p, g)))
