@@ -21,7 +21,10 @@ n uniform in 8..24, one fused launch), serve (Poisson-arrival geodesic and
 Schur requests through the request loop; p50/p99 latency), schur_odd (exact
 perm(S_n) for odd n through checkpointed CRT jobs with a redundant prime),
 stats (50,000 Haar U(n) and O(n) permanents per odd n in 7..23 and their
-distribution checks), dft (the DFT-geodesic fingerprint r(n)).
+distribution checks), dft (the DFT-geodesic fingerprint r(n)), shard (one
+GPU's share of perm(S_36) spread over eight: eight Gray-index ranges through
+perm_range, whose partials must add up to the single call's residue), sizes
+(one matrix per call at orders 20..36).
 
 Prints one JSON line.  The oracle (CPU Ryser) is timed on a bounded prefix of
 the same computation for the "cpu_baseline" field.
@@ -915,7 +918,7 @@ def sub_sizes(P, ctx, args):
     one prime (F_p) for n = 22..36.  Per case: the call's time and terms/s
     and the walk kernel's fraction of the FP64 VALU peak; the record's
     roofline is over all cases (their algorithmic instructions over their
-    summed walk time).  Single calls of orders 16..27 use the latency
+    summed walk time).  Single calls of orders 10..27 use the latency
     partition (shorter wave items, so that one matrix occupies the device);
     from order 28 the batch partition already does."""
     import torch
@@ -1069,7 +1072,49 @@ def bench_schur_odd(P, ctx, args):
             "runs": runs}
 
 
-WORKLOADS = {"default": bench_default, "dft": bench_dft, "stats": bench_stats, "schur_odd": bench_schur_odd, "copycal": bench_copycal, "serve": bench_serve, "schur28": bench_schur, "single14": bench_single14, "haar20": bench_haar20,
+def bench_shard(P, ctx, args):
+    """One GPU's share of a permanent spread over G GPUs: perm(S_n) mod its
+    first prime, the Gray range [0, 2^(n-1)) cut into G equal ranges, each
+    walked through perm_range as GPU g would walk it (the same kernel and
+    wave items as the whole walk).  The G ranges run here one after another;
+    their unscaled partials must add up, mod p, to the residue of the single
+    call.  `value` is one shard's Glynn-term rate (median over the shards)."""
+    n, G = args.shard_n, args.shards
+    T = 1 << (n - 1)
+    if G < 1 or T % G:
+        raise SystemExit(f"--shards must divide 2^{n - 1}")
+    p = P.perm_schur_primes(n)[0]
+    A = P.perm_schur_residues(n, p)
+    items, data = P.pack_matrices([(A, "modp", p)])
+    P.perm_range(ctx, items[0], data, 0, T // G)              # warm-up
+    P.perm_prof_enable(ctx, True)
+    P.perm_prof_read(ctx)
+    parts, walls = [], []
+    for k in range(G):
+        t0 = time.perf_counter()
+        parts.append(int(P.perm_range(ctx, items[0], data, k * T // G, (k + 1) * T // G)))
+        walls.append(time.perf_counter() - t0)
+    walk_ms, launches = P.perm_prof_read(ctx)
+    P.perm_prof_enable(ctx, False)
+    t0 = time.perf_counter()
+    whole = P.perm_modp(ctx, A, p)
+    whole_s = time.perf_counter() - t0
+    combined = sum(parts) % p * pow((p + 1) // 2, n - 1, p) % p
+    assert combined == whole, f"shards give {combined}, the single call {whole}"
+    med = float(np.median(walls))
+    rec = {"metric": METRIC, "value": (T // G) / med, "unit": "subset-terms/s",
+           "ms_per_step": med * 1e3, "dtype": "f64",
+           "config": {"workload": "schur_shard", "n": n, "shards": G, "prime": p,
+                      "terms_per_shard": T // G},
+           "roofline": roofline((T // G) * ops_per_term("modp", n), walk_ms, launches, None),
+           "shard_ms": [round(w * 1e3, 3) for w in walls], "shard_partials": parts,
+           "residue": whole, "single_call_s": whole_s}
+    if not args.no_cpu:
+        rec["cpu_baseline"] = cpu_baseline_schur(n, [p])
+    return rec
+
+
+WORKLOADS = {"default": bench_default, "shard": bench_shard, "dft": bench_dft, "stats": bench_stats, "schur_odd": bench_schur_odd, "copycal": bench_copycal, "serve": bench_serve, "schur28": bench_schur, "single14": bench_single14, "haar20": bench_haar20,
              "ragged": bench_ragged, "sizes": bench_sizes}
 
 
@@ -1090,6 +1135,8 @@ def main():
     ap.add_argument("--n-list", default="29,31,33,35,37,39",
                     help="schur_odd: odd orders to run")
     ap.add_argument("--extra", type=int, default=1, help="schur_odd: redundant primes")
+    ap.add_argument("--shard-n", type=int, default=36, help="shard: order of the Schur matrix")
+    ap.add_argument("--shards", type=int, default=8, help="shard: GPUs the permanent is spread over")
     ap.add_argument("--checkpoint-dir", default=None,
                     help="schur_odd: keep (and resume from) checkpoints here")
     args = ap.parse_args()

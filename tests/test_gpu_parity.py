@@ -249,6 +249,49 @@ def test_range_partials_large_orders(P, ctx, O, field, n):
             assert got == O.native.glynn_range_modp(A, p, x0, x1)
 
 
+@pytest.mark.parametrize("field,n,G", [("modp", 21, 8), ("c128", 20, 4), ("f64", 21, 8),
+                                       ("modp", 29, 8)])
+def test_range_shards_add_up(P, ctx, O, field, n, G):
+    """Spreading one permanent over G GPUs gives GPU g the Gray range
+    [g T/G, (g+1) T/G), T = 2^(n-1), through perm_range, at the wave-item
+    shape of the whole walk.  Walked here one after another, each shard's
+    unscaled partial equals the oracle's direct Glynn sum over its range
+    (orders up to 21), and the shards add up to the whole permanent: mod p
+    exactly (S_29 against the single call, its oracle being too slow), for
+    floats within the tolerance of the oracle's permanent."""
+    T = 1 << (n - 1)
+    p = 1073742209
+    g = E.rng(18, n)
+    if field == "modp" and n > 21:
+        p = P.perm_schur_primes(n)[0]
+        A = P.perm_schur_residues(n, p)
+    elif field == "modp":
+        A = E.random_residues(n, p, g)
+    elif field == "c128":
+        A = E.haar_unitary(n, g)
+    else:
+        A = E.haar_orthogonal(n, g)
+    items, data = P.pack_matrices([(A, field, p if field == "modp" else 0)])
+    parts = [P.perm_range(ctx, items[0], data, k * T // G, (k + 1) * T // G) for k in range(G)]
+    if field == "modp":
+        total = sum(int(v) for v in parts) % p
+        if n <= 21:
+            for k, v in enumerate(parts):
+                assert v == O.native.glynn_range_modp(A, p, k * T // G, (k + 1) * T // G)
+            want = O.native.ryser_modp(A, p)
+        else:
+            want = P.perm_modp(ctx, A, p)
+        assert total * pow((p + 1) // 2, n - 1, p) % p == want
+        return
+    rng_fn = O.native.glynn_range_c128 if field == "c128" else O.native.glynn_range_f64
+    for k, v in enumerate(parts):
+        want = rng_fn(A, k * T // G, (k + 1) * T // G)
+        assert abs(v - want) <= TOL * scale(A) * (T // G) ** 0.5
+    whole = math.ldexp(1.0, -(n - 1)) * sum(parts)
+    want = O.native.ryser_c128(A) if field == "c128" else O.native.ryser_f64(A)
+    assert abs(whole - want) <= TOL * scale(A)
+
+
 def test_range_rejects_bad_bounds(P, ctx):
     items, data = P.pack_matrices([(np.eye(5), "f64", 0)])
     with pytest.raises(P.PermError) as e:
