@@ -42,10 +42,10 @@
  *   partition of (field, n) in the tuning table, or the library default,
  *   whatever else the batch holds, so a float result has the same bits in
  *   every batch and in the server.  A call whose items at that length would
- *   leave resident waves idle (one matrix of order up to about 27, a few F_p
- *   residue matrices) instead uses the latency partition: the chunk length
- *   that minimises the call's time, down to 2^4 (a table entry for (field,
- *   n) turns it off).  F_p results are exact under any partition.  A single
+ *   leave resident waves idle (one matrix of order 10 to about 27, a few
+ *   F_p residue matrices) instead uses the latency partition: the chunk
+ *   length that minimises the call's time, down to 2^3 (a table entry for
+ *   (field, n) turns it off).  F_p results are exact under any partition.  A single
  *   float call (perm_c128, perm_f64) therefore agrees with the same matrix
  *   in a batch to within rounding (1e-10 of prod_i ||row_i||_2 is the tested
  *   bound), and bit for bit when called with PERM_SHARED_PARTITION, which
