@@ -247,14 +247,17 @@ int latency_log2_chunk(const perm_ctx *ctx, int variant, int n, uint64_t nmats, 
     // item cost: the seed's instructions -- the wave's common part (about n
     // a lane) and the seven columns whose signs differ across its lanes,
     // each an update of the n row sums (two words each for c128; the
-    // Montgomery walk updates for all n - 1 columns) -- and about 1,860 slots
-    // of latency and overhead (claim, loads of the descriptors and the
-    // matrix, LDS exchange, wave sum), fitted to single calls of orders
-    // 10..23 timed at every chunk length: 2^3 fastest up to order 20, then
-    // one wave per SIMD (2^4 at 21, 2^5 at 22) rather than two of half the
-    // length
+    // Montgomery walk updates for all n - 1 columns) -- and a fixed part for
+    // latency and overhead (claim, loads of the descriptors and the matrix,
+    // LDS exchange, wave sum), fitted to single calls of orders 10..27 timed
+    // at every chunk length: 2^3 fastest up to order 20, then one wave per
+    // SIMD (2^4 at 21, 2^5 at 22) rather than two of half the length; the
+    // Barrett F_p walk kept one wave per SIMD up to order 24 (2^7; two waves
+    // of 2^6 were 2-7% slower from order 22) and two from 25, which takes a
+    // fixed part of about 16,000 slots, the float walks about 1,860
     const int upd = variant == V_MONT ? n - 1 : std::min(n - 1, 7);
-    const double item = (double)upd * n * (variant == V_C128 ? 2.0 : 1.0) + n + 1860.0;
+    const double fixed = variant == V_MODP ? 16000.0 : 1860.0;
+    const double item = (double)upd * n * (variant == V_C128 ? 2.0 : 1.0) + n + fixed;
     const double step = (double)step_cost(variant, n);
     const double simds = (double)ctx->num_cus * (BLOCK / WAVE);
     int best = c0;
