@@ -96,3 +96,12 @@ def test_range_baseline_is_scaled_to_glynn_terms():
     r = bench.cpu_baseline_range(E.haar_unitary(20, E.rng(90, 0)), "c128", seconds=0.1)
     assert r["kind"] == "oracle" and r["value"] > 0 and r["cores"] >= 1
     assert r["unit"].startswith("subset-terms/s") and "order 20" in r["sample"]
+
+
+def test_shard_count_must_divide_the_range():
+    """The shard workload cuts [0, 2^(n-1)) into equal Gray ranges; a count
+    that does not divide it is refused before any device work."""
+    import argparse
+    args = argparse.Namespace(shard_n=36, shards=3, no_cpu=True)
+    with pytest.raises(SystemExit):
+        bench.bench_shard(None, None, args)
