@@ -313,7 +313,7 @@ def test_batch_mixed_matches_single_bitwise(P, ctx, O):
     for (A, field, p), v in zip(mats, vals):
         n = A.shape[0]
         # a single call with the batch partition has the batch's bits; the
-        # default single call (the latency partition from order 16) agrees
+        # default single call (the latency partition from order 10) agrees
         # to within the tolerance
         if field == "c128":
             assert v == P.perm_c128(ctx, A, flags=P.PERM_SHARED_PARTITION)
