@@ -396,7 +396,10 @@ def sub_single14(P, ctx, args, calls=200, groups=5):
     """Config 1: one 14x14 Haar unitary per call, device pointers, result
     left on the device; median per-call time over `groups` groups of
     `calls` back-to-back calls.  Timing events add about 9 us to a call, so
-    the kernel duration comes from a second, profiled pass."""
+    the kernel duration comes from a second, profiled pass.  Beside it: the
+    same call through perm_c128_noalloc, each call waited for before the
+    next (isolated latency), and the matrix handed over in host memory with
+    the result returned to the host (both copies inside the call)."""
     import torch
     from paper_2602_10141_amd import ensembles as E
     A = E.haar_unitary(14, E.rng(1, 0))
@@ -428,9 +431,24 @@ def sub_single14(P, ctx, args, calls=200, groups=5):
             P.perm_c128_noalloc(ctx, U, out=out)
         sync()
         na.append((time.perf_counter() - t0) / calls)
+    # isolated calls: each waited for before the next (result on the device),
+    # and from host memory to a Python complex (both copies inside the call)
+    iso, host = [], []
+    for _ in range(groups):
+        t0 = time.perf_counter()
+        for _ in range(calls):
+            P.perm_c128(ctx, U)
+            sync()
+        iso.append((time.perf_counter() - t0) / calls)
+        t0 = time.perf_counter()
+        for _ in range(calls):
+            P.perm_c128(ctx, A)
+        host.append((time.perf_counter() - t0) / calls)
     rec = {"workload": "haar_unitary_14_c128", "n": 14, "value": 1.0 / med, "unit": "perms/s",
            "us_per_call_median": med * 1e6, "timed": f"{groups} groups of {calls} calls",
-           "noalloc_us_per_call_median": float(np.median(na)) * 1e6, "dtype": "c128",
+           "noalloc_us_per_call_median": float(np.median(na)) * 1e6,
+           "isolated_us_per_call_median": float(np.median(iso)) * 1e6,
+           "host_buffers_us_per_call_median": float(np.median(host)) * 1e6, "dtype": "c128",
            "roofline": roofline((1 << 13) * ops_per_term("c128", 14), walk_ms, launches, None,
                                 flops_per_op("c128", 14))}
     if not args.no_cpu:
