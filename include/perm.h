@@ -27,7 +27,8 @@
  *   such a call is ordered with PyTorch's work there and with every blocking
  *   stream.  A single-matrix call's device output aligned to its element
  *   type is written by the kernels directly (exactly its bytes), otherwise
- *   through a device copy.
+ *   through a device copy; a host output is written by the kernels into a
+ *   pinned slot of the context and copied from there once they are done.
  * - The caller owns every buffer it passes.  The context owns only its
  *   device scratch (staged matrices, partial sums, plans), which grows on
  *   demand up to the context's HBM budget and is reused across calls.

@@ -121,6 +121,25 @@ static int ensure_pinned(perm_ctx *ctx, size_t bytes)
     return PERM_OK;
 }
 
+// The pinned 16-byte result slot of host-pointer single calls.
+static int ensure_host_out(perm_ctx *ctx)
+{
+    if (ctx->host_out) return PERM_OK;
+    void *p = nullptr, *d = nullptr;
+    if (hipHostMalloc(&p, 256, hipHostMallocDefault) != hipSuccess) {
+        (void)hipGetLastError();
+        return fail(PERM_ENOMEM, "hipHostMalloc(256) failed");
+    }
+    if (hipHostGetDevicePointer(&d, p, 0) != hipSuccess) {
+        (void)hipGetLastError();
+        (void)hipHostFree(p);
+        return fail(PERM_EDEVICE, "hipHostGetDevicePointer failed");
+    }
+    ctx->host_out = p;
+    ctx->host_out_dev = d;
+    return PERM_OK;
+}
+
 // ------------------------------------------------------------------ tuning
 int default_log2_chunk(int variant, int n)
 {
@@ -731,6 +750,7 @@ extern "C" void perm_ctx_destroy(perm_ctx *c)
     for (DevBuf *b : {&c->src, &c->stage, &c->partials, &c->outs, &c->plan_buf, &c->ctr})
         if (b->p) (void)hipFree(b->p);
     if (c->pinned) (void)hipHostFree(c->pinned);
+    if (c->host_out) (void)hipHostFree(c->host_out);
     for (auto *v : {&c->prof_pending, &c->prof_pool})
         for (auto &e : *v) {
             (void)hipEventDestroy(e.first);
@@ -803,16 +823,20 @@ static int single(perm_ctx *ctx, int variant, const void *A, int n, uint32_t p, 
         if ((rc = execute(ctx, pl, src, out, 1, s)) != PERM_OK) return rc;
         return end_call(ctx, s);
     }
+    if (!(flags & PERM_DEVICE_PTRS)) {
+        // a host output: the finalize step writes the slot in pinned host
+        // memory (free here: the previous such call waited for its kernels)
+        if ((rc = ensure_host_out(ctx)) != PERM_OK) return rc;
+        if ((rc = execute(ctx, pl, src, ctx->host_out_dev, 1, s)) != PERM_OK) return rc;
+        if ((rc = end_call(ctx, s)) != PERM_OK) return rc;
+        HIPCHK(hipStreamSynchronize(s));
+        std::memcpy(out, ctx->host_out, out_bytes);
+        return PERM_OK;
+    }
     if ((rc = ensure(ctx, ctx->outs, 256)) != PERM_OK) return rc;
     if ((rc = execute(ctx, pl, src, ctx->outs.p, 1, s)) != PERM_OK) return rc;
-    if (flags & PERM_DEVICE_PTRS) {
-        HIPCHK(hipMemcpyAsync(out, ctx->outs.p, out_bytes, hipMemcpyDeviceToDevice, s));
-        return end_call(ctx, s);
-    }
-    HIPCHK(hipMemcpyAsync(out, ctx->outs.p, out_bytes, hipMemcpyDeviceToHost, s));
-    if ((rc = end_call(ctx, s)) != PERM_OK) return rc;
-    HIPCHK(hipStreamSynchronize(s));
-    return PERM_OK;
+    HIPCHK(hipMemcpyAsync(out, ctx->outs.p, out_bytes, hipMemcpyDeviceToDevice, s));
+    return end_call(ctx, s);
 }
 
 extern "C" int perm_c128(perm_ctx *ctx, const double *A, int n, double *out, unsigned flags,

@@ -35,6 +35,7 @@ hipError_t hipMalloc(void **, size_t);
 hipError_t hipFree(void *);
 hipError_t hipHostMalloc(void **, size_t, unsigned);
 hipError_t hipHostFree(void *);
+hipError_t hipHostGetDevicePointer(void **, void *, unsigned);
 hipError_t hipMemset(void *, int, size_t);
 hipError_t hipMemsetAsync(void *, int, size_t, hipStream_t);
 hipError_t hipMemcpyAsync(void *, const void *, size_t, hipMemcpyKind, hipStream_t);

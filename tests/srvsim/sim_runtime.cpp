@@ -173,6 +173,11 @@ hipError_t hipMalloc(void **p, size_t n)
 hipError_t hipFree(void *p) { free(p); return hipSuccess; }
 hipError_t hipHostMalloc(void **p, size_t n, unsigned) { return hipMalloc(p, n); }
 hipError_t hipHostFree(void *p) { free(p); return hipSuccess; }
+hipError_t hipHostGetDevicePointer(void **d, void *h, unsigned)
+{
+    *d = h;                        // one address space here
+    return hipSuccess;
+}
 hipError_t hipMemset(void *p, int v, size_t n)
 {
     sim_enqueue(nullptr, [=] { memset(p, v, n); });
