@@ -77,10 +77,12 @@ struct perm_ctx {
     size_t pinned_cap = 0;
     hipEvent_t pinned_ev = nullptr;
     bool pinned_busy = false;
-    // pinned result slot of host-pointer single calls, written by the
-    // finalize step through its device address (no copy launch)
+    // pinned result slots of calls whose results go to the host (single
+    // calls with a host output, CRT residues), written by the finalize step
+    // through their device address (no copy launch)
     void *host_out = nullptr;
     void *host_out_dev = nullptr;
+    size_t host_out_cap = 0;
     permk::CtrState ctr_state;
     int grid_per_cu = 0;
     std::map<std::pair<int, int>, perm_tune> tune;

@@ -121,14 +121,20 @@ static int ensure_pinned(perm_ctx *ctx, size_t bytes)
     return PERM_OK;
 }
 
-// The pinned 16-byte result slot of host-pointer single calls.
-static int ensure_host_out(perm_ctx *ctx)
+// Pinned result slots (at least `bytes`) for calls that return their
+// results to the host.  Such calls wait for their kernels before returning,
+// so the slots are free at the next call.
+static int ensure_host_out(perm_ctx *ctx, size_t bytes)
 {
-    if (ctx->host_out) return PERM_OK;
+    if (bytes <= ctx->host_out_cap) return PERM_OK;
+    if (ctx->host_out) HIPCHK(hipHostFree(ctx->host_out));
+    ctx->host_out = ctx->host_out_dev = nullptr;
+    ctx->host_out_cap = 0;
+    const size_t want = std::max(bytes, (size_t)4096);
     void *p = nullptr, *d = nullptr;
-    if (hipHostMalloc(&p, 256, hipHostMallocDefault) != hipSuccess) {
+    if (hipHostMalloc(&p, want, hipHostMallocDefault) != hipSuccess) {
         (void)hipGetLastError();
-        return fail(PERM_ENOMEM, "hipHostMalloc(256) failed");
+        return fail(PERM_ENOMEM, "hipHostMalloc(%zu) failed", want);
     }
     if (hipHostGetDevicePointer(&d, p, 0) != hipSuccess) {
         (void)hipGetLastError();
@@ -137,6 +143,7 @@ static int ensure_host_out(perm_ctx *ctx)
     }
     ctx->host_out = p;
     ctx->host_out_dev = d;
+    ctx->host_out_cap = want;
     return PERM_OK;
 }
 
@@ -826,7 +833,7 @@ static int single(perm_ctx *ctx, int variant, const void *A, int n, uint32_t p, 
     if (!(flags & PERM_DEVICE_PTRS)) {
         // a host output: the finalize step writes the slot in pinned host
         // memory (free here: the previous such call waited for its kernels)
-        if ((rc = ensure_host_out(ctx)) != PERM_OK) return rc;
+        if ((rc = ensure_host_out(ctx, 16)) != PERM_OK) return rc;
         if ((rc = execute(ctx, pl, src, ctx->host_out_dev, 1, s)) != PERM_OK) return rc;
         if ((rc = end_call(ctx, s)) != PERM_OK) return rc;
         HIPCHK(hipStreamSynchronize(s));
@@ -1185,12 +1192,12 @@ extern "C" int perm_crt_int(perm_ctx *ctx, const uint32_t *mats, const uint32_t 
     }
     Plan &pl = ctx->scratch_plan;
     if ((rc = plan(ctx, in, pl)) != PERM_OK) return rc;
-    if ((rc = ensure(ctx, ctx->outs, (size_t)k * 16)) != PERM_OK) return rc;
-    if ((rc = execute(ctx, pl, src, ctx->outs.p, (size_t)k, s)) != PERM_OK) return rc;
-    std::vector<uint32_t> slots((size_t)k * 4);
-    HIPCHK(hipMemcpyAsync(slots.data(), ctx->outs.p, (size_t)k * 16, hipMemcpyDeviceToHost, s));
+    // the residues' slots in pinned host memory, written by the finalize step
+    if ((rc = ensure_host_out(ctx, (size_t)k * 16)) != PERM_OK) return rc;
+    if ((rc = execute(ctx, pl, src, ctx->host_out_dev, (size_t)k, s)) != PERM_OK) return rc;
     if ((rc = end_call(ctx, s)) != PERM_OK) return rc;
     HIPCHK(hipStreamSynchronize(s));
+    const uint32_t *slots = (const uint32_t *)ctx->host_out;
     std::vector<uint32_t> res(k);
     for (int i = 0; i < k; ++i) res[i] = slots[4 * (size_t)i];
     permh::BigU mag;
