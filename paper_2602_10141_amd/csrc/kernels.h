@@ -38,7 +38,9 @@ struct MatDesc {
     double   pinv;        // 1/p rounded to binary64 (V_MODP)
     uint32_t mont_pp;     // -p^{-1} mod 2^32 (V_MONT)
     uint32_t out_slot;    // result slot (16 bytes each) in the output buffer
-    uint32_t pad[2];
+    uint32_t fin_scale;   // F_p: what finalize multiplies the residue sum by, mod p:
+                          //   inv(2)^(n-1) (1 with MD_NO_SCALE), times R^(n-1) for V_MONT
+    uint32_t pad;
 };
 static_assert(sizeof(MatDesc) == 64, "MatDesc layout");
 

@@ -23,6 +23,16 @@ uint64_t powmod(uint64_t b, uint64_t e, uint64_t m)
     return r;
 }
 
+uint32_t fp_finalize_factor(uint32_t p, int n, bool montgomery, bool scaled)
+{
+    if (p < 3) return 0;
+    const uint64_t e = n > 1 ? (uint64_t)(n - 1) : 0;
+    uint64_t f = 1;
+    if (montgomery) f = powmod((1ull << 32) % p, e, p);
+    if (scaled) f = mulmod64(f, powmod((p + 1) / 2, e, p), p);
+    return (uint32_t)f;
+}
+
 // Deterministic Miller-Rabin for m < 2^32 (bases 2, 3, 5, 7 suffice below 3.2e9).
 bool is_prime_u32(uint32_t m)
 {

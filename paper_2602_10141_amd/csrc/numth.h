@@ -16,6 +16,10 @@ uint32_t root_of_unity(int n, uint32_t p);
 std::vector<uint32_t> primes_1_mod_n(int n, int count);
 // -p^{-1} mod 2^32 for odd p.
 uint32_t mont_pprime(uint32_t p);
+// What the F_p finalize step multiplies a residue sum of an order-n walk by:
+// inv(2)^(n-1) against Glynn's 2^(n-1) (1 when `scaled` is false), times
+// R^(n-1), R = 2^32, for Montgomery sums, whose products leave R^-(n-1).
+uint32_t fp_finalize_factor(uint32_t p, int n, bool montgomery, bool scaled);
 
 // Non-negative multi-limb integer, little-endian uint64 limbs, no leading zeros.
 struct BigU {

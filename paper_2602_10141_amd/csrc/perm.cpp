@@ -416,6 +416,8 @@ int plan(perm_ctx *ctx, const std::vector<MatIn> &in, Plan &pl)
                   (a.out_bytes == 8 ? MD_OUT_8 : 0) | (a.out_bytes == 4 ? MD_OUT_4 : 0);
         d.pinv = a.p ? 1.0 / (double)a.p : 0.0;
         d.mont_pp = (a.variant == V_MONT) ? permh::mont_pprime(a.p) : 0;
+        if (a.variant == V_MODP || a.variant == V_MONT)
+            d.fin_scale = permh::fp_finalize_factor(a.p, a.n, a.variant == V_MONT, !a.no_scale);
         d.out_slot = a.out_slot;
         if (a.n > 0) pl.stage_bytes += (stage_bytes(a.variant, a.n) + 255) & ~(size_t)255;
     }

@@ -252,6 +252,8 @@ void layout(perm_srv *S, Req &r)
     d.flags = (S->cfg.flags & PERM_NO_KAHAN) ? 0 : MD_KAHAN;
     d.pinv = r.p ? 1.0 / (double)r.p : 0.0;
     d.mont_pp = r.variant == V_MONT ? permh::mont_pprime(r.p) : 0;
+    if (r.variant == V_MODP || r.variant == V_MONT)
+        d.fin_scale = permh::fp_finalize_factor(r.p, r.n, r.variant == V_MONT, true);
     d.out_slot = 0;
     // items: the same split perm_batch makes of the full range [0, 2^(n-1))
     r.nitems = 0;

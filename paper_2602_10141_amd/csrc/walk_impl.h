@@ -818,22 +818,12 @@ __device__ inline void stage_one(const MatDesc md, const char *src, char *stage)
 // ---------------------------------------------------------------- finalize
 // Per matrix, with the 256 threads of a block: reduce its partial slots in a
 // fixed order (strided compensated sums, then a fixed tree), apply
-// 2^{-(n-1)} (floats) or inv(2)^{n-1} (F_p; Montgomery's R^{-(n-1)} too),
+// 2^{-(n-1)} (floats) or the host's factor md.fin_scale (F_p: inv(2)^{n-1},
+// and for Montgomery R^{n-1} against the R^{-(n-1)} its products leave),
 // write the 16-byte result slot (only its first 8 or 4 bytes with MD_OUT_8
-// or MD_OUT_4: a caller's f64 or F_p output written in place).  Shared by finalize_kernel and by walk
-// launches of one block, which finalize their own matrices, so the two give
-// identical bits.  sa, sb, su: 256 entries each in LDS.
-__device__ inline uint64_t powmod_u64(uint64_t b, uint32_t e, uint64_t p)
-{
-    uint64_t r = 1 % p;
-    b %= p;
-    while (e) {
-        if (e & 1) r = (r * b) % p;
-        b = (b * b) % p;
-        e >>= 1;
-    }
-    return r;
-}
+// or MD_OUT_4: a caller's f64 or F_p output written in place).  Shared by
+// finalize_kernel and by walk launches that finalize their own matrices, so
+// the two give identical bits.  sa, sb, su: 256 entries each in LDS.
 
 static_assert(BLOCK == 256, "finalize_one reduces with 256 threads");
 __device__ inline void finalize_one(const MatDesc md, const double *partials, char *out,
@@ -866,16 +856,14 @@ __device__ inline void finalize_one(const MatDesc md, const double *partials, ch
         su[t] = acc % P;
         __syncthreads();
         for (int w = 128; w >= 1; w >>= 1) {
-            if (t < w) su[t] = (su[t] + su[t + w]) % P;
+            if (t < w) {                    // both below P < 2^31: one subtraction reduces
+                const unsigned long long v = su[t] + su[t + w];
+                su[t] = v >= P ? v - P : v;
+            }
             __syncthreads();
         }
         if (t == 0) {
-            uint64_t v = su[0];
-            // Montgomery products leave R^{-(n-1)}; Glynn leaves 2^{n-1}.
-            uint64_t f = 1;
-            if (md.variant == V_MONT) f = powmod_u64((1ull << 32) % P, md.n - 1, P);
-            if (!(md.flags & MD_NO_SCALE)) f = (f * powmod_u64((P + 1) / 2, md.n - 1, P)) % P;
-            v = (v * f) % P;
+            const uint64_t v = (su[0] * (uint64_t)md.fin_scale) % P;
             ((uint32_t *)o)[0] = (uint32_t)v;
             if (!(md.flags & MD_OUT_4))
                 ((uint32_t *)o)[1] = ((uint32_t *)o)[2] = ((uint32_t *)o)[3] = 0u;

@@ -42,6 +42,18 @@ static void check_plan(const perm_ctx *ctx, const std::vector<MatIn> &in, const 
         CHECK(d.n == in[m].n && d.variant == in[m].variant && d.out_slot == in[m].out_slot, "desc %zu", m);
         CHECK(d.stage_off % 256 == 0 && d.stage_off >= next_stage, "stage %zu", m);
         if (in[m].n > 0) next_stage = d.stage_off + stage_bytes(d.variant, d.n);
+        // F_p finalize factor: f 2^(n-1) = R^(n-1) (Montgomery) or 1 (Barrett)
+        // mod p for a whole permanent, f = R^(n-1) or 1 for an unscaled sum
+        if ((d.variant == V_MODP || d.variant == V_MONT) && d.n > 0) {
+            const uint64_t p = d.p, e = (uint64_t)d.n - 1;
+            uint64_t want = 1, two = 1;
+            for (uint64_t i = 0; i < e; ++i) {
+                if (d.variant == V_MONT) want = want * ((1ull << 32) % p) % p;
+                two = two * 2 % p;
+            }
+            const uint64_t got = in[m].no_scale ? d.fin_scale : (uint64_t)d.fin_scale * two % p;
+            CHECK(got == want, "desc %zu: F_p finalize factor", m);
+        }
     }
     // items per matrix tile the range once, slots once each
     std::vector<std::vector<const WaveItem *>> per(in.size());
